@@ -1,0 +1,189 @@
+"""Time-to-solution and preconditioner throughput of the FlashMP hot path on one GPU.
+
+Workload: 256^3 Yee grid with PEC walls, 8 x 8 x 8 subdomains of 32^3 cells
+(overlap 1), eps_r ~ U[1,10] on 8^3-cell cubes, c = 2, right-hand side N(0,1)
+(seed 3).  One step = one full FGMRES(30) solve in FP64 to a relative residual
+of 1e-8 from x0 = 0, with the FlashMP RAS preconditioner (FP64 transforms).
+Variants (FP32 transforms) are timed the same way and reported beside it.
+
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = ("time-to-solution at rel. residual 1e-8 (256³) + precond applies/s; "
+          "plain vs mixed/learned")
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(P, iters, sample_boxes=12):
+    """Time the CPU oracle on a bounded sample of one FGMRES iteration's work and scale it.
+
+    Sample: `sample_boxes` of the 512 subdomain solves (scaled to 512), one
+    sparse A x on a 64^3 sub-grid (scaled by unknown count), and one dot and
+    one axpy on full 256^3 vectors (scaled to the CGS work of an average
+    Arnoldi step, j = 15: 2j + 5 vector passes).  Reported as the estimated
+    time-to-solution for the same iteration count as the GPU run.
+    """
+    from oracle import ras, yee
+    n = P["nx"]
+    eps_cell = yee.expand_eps(P["eps"], P["eps_block"], n, n, n)
+    nsub = (n // P["sub"][0]) ** 3
+    which = list(np.linspace(0, nsub - 1, sample_boxes).astype(int))
+    t0 = time.perf_counter()
+    ras.ras_apply_subset(P["rhs"], P["c"], P["sub"], 1, eps_cell, which)
+    t_pre = (time.perf_counter() - t0) * nsub / sample_boxes
+    m = 64
+    A = yee.assemble_A(m, m, m, P["c"], eps_cell[:m, :m, :m])
+    xs = yee.from_padded(P["rhs"][:, :m, :m, :m])
+    t0 = time.perf_counter()
+    for _ in range(3):
+        A @ xs
+    t_spmv = (time.perf_counter() - t0) / 3 * (yee.n_unknowns(n, n, n) / xs.size)
+    a = P["rhs"].ravel()
+    b = np.roll(a, 1)
+    t0 = time.perf_counter()
+    float(np.dot(a, b))
+    c = a + 0.5 * b
+    t_vec = (time.perf_counter() - t0) / 2
+    del c
+    per_it = t_pre + t_spmv + (2 * 15 + 5) * t_vec
+    total = per_it * iters
+    return dict(value=round(total * 1e3, 1), unit="ms", cores=os.cpu_count(), kind="oracle",
+                sample=(f"{sample_boxes}/{nsub} subdomain solves, one 64^3 sparse A x, one dot + "
+                        f"axpy on 256^3 vectors, scaled to {iters} FGMRES iterations "
+                        f"({per_it * 1e3:.0f} ms per iteration)"),
+                seconds_measured=round((t_pre * sample_boxes / nsub) + t_spmv / 1 + t_vec, 2))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c3")
+    ap.add_argument("--variants", default="fp32")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the solver has no multi-GPU path "
+              "(see DESIGN.md for how it would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2508_07193_amd import api, inputs
+
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    P = inputs.make_problem(args.config)
+    n = P["nx"]
+    dom = dict(nx=n, ny=n, nz=n, c=P["c"], eps=P["eps"], eps_block=P["eps_block"], sub=P["sub"])
+    b = torch.from_numpy(P["rhs"].ravel()).to(dev)
+    n_unk = inputs.n_unknowns(n, n, n)
+    stream = torch.cuda.current_stream()
+
+    def run_solves(h, steps, warmup, tag):
+        x = h.new_vector()
+        info = None
+        for _ in range(warmup):
+            x.zero_()
+            info = h.solve(b, x, solver="fgmres", restart=30, rtol=1e-8, max_iter=500)
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(steps):
+            x.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = h.solve(b, x, solver="fgmres", restart=30, rtol=1e-8, max_iter=500)
+            torch.cuda.synchronize()
+            times.append((time.perf_counter() - t0) * 1e3)
+        log(f"[{tag}] solve: {info}  ms={times}")
+        return x, info, float(np.mean(times))
+
+    def time_events(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    # ---------------- plain FP64 FlashMP
+    h = api.Handle([dom], overlap=1, precision="fp64", device=dev)
+    log(f"handle ready: workspace {h.ws.numel() / 2**20:.0f} MiB, vector {h.length} doubles")
+    x64, info64, tts64 = run_solves(h, args.steps, args.warmup, "fp64")
+    z = h.new_vector()
+    y = h.new_vector()
+    t_pre = time_events(lambda: h.apply_precond(b, z), 10)
+    t_spmv = time_events(lambda: h.curlcurl_apply(b, y), 20)
+    spmv_bytes = 16.0 * n_unk
+    roof_spmv = dict(bound="hbm", achieved=round(spmv_bytes / (t_spmv * 1e-3) / 1e9, 1),
+                     peak=HBM_PEAK_GBS, unit="GB/s", traffic=None, kernel="k_curlcurl",
+                     bytes_per_launch=spmv_bytes, avg_ms=round(t_spmv, 4))
+    roof_spmv["frac"] = round(roof_spmv["achieved"] / HBM_PEAK_GBS, 3)
+    pre_bytes = 16.0 * n_unk
+    out = {
+        "metric": METRIC, "value": round(tts64, 2), "unit": "ms", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(tts64, 2),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "256^3 Yee grid, PEC walls, 8^3 subdomains of 32^3 (overlap 1), "
+                               "eps_r U[1,10] on 8^3 cubes, c=2, RHS N(0,1) seed 3; FGMRES(30) "
+                               "FP64 to rel. residual 1e-8 with FlashMP RAS (FP64 transforms)",
+                   "unknowns": n_unk, "solver": "fgmres(30)", "rtol": 1e-8},
+        "iterations": info64["iterations"],
+        "rel_residual_true": info64["rel_residual_true"],
+        "precond_applies_per_s": round(1e3 / t_pre, 1),
+        "precond_ms": round(t_pre, 4),
+        "precond_hbm_gbs_min_traffic": round(pre_bytes / (t_pre * 1e-3) / 1e9, 1),
+        "spmv_ms": round(t_spmv, 4),
+        "roofline": roof_spmv,
+        "variants": {},
+    }
+    ref = x64.clone()
+    del h
+    torch.cuda.empty_cache()
+
+    for prec in [v for v in args.variants.split(",") if v]:
+        try:
+            hv = api.Handle([dom], overlap=1, precision=prec, device=dev)
+            xv, infov, ttsv = run_solves(hv, max(1, args.steps), args.warmup, prec)
+            zv = hv.new_vector()
+            tpv = time_events(lambda: hv.apply_precond(b, zv), 10)
+            err = float(torch.linalg.vector_norm(xv - ref) / torch.linalg.vector_norm(ref))
+            out["variants"][prec] = dict(time_to_solution_ms=round(ttsv, 2),
+                                         iterations=infov["iterations"],
+                                         rel_residual_true=infov["rel_residual_true"],
+                                         precond_applies_per_s=round(1e3 / tpv, 1),
+                                         precond_ms=round(tpv, 4),
+                                         rel_err_vs_fp64_solution=err,
+                                         speedup_vs_fp64=round(tts64 / ttsv, 3))
+            del hv
+            torch.cuda.empty_cache()
+        except Exception as e:  # report, do not hide
+            out["variants"][prec] = dict(error=str(e))
+
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(P, info64["iterations"])
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,196 @@
+/*
+ * flashmp.h - C ABI of the FlashMP hot path on one AMD Instinct MI355X (gfx950).
+ *
+ * The library solves the Crank-Nicolson FDTD double-curl system
+ *     A E = b,   A = I + c diag(1/eps_e) K,   K = C^T C   (Sec. II-A, eqs. (4)-(5);
+ *                                                         Sec. III-A, eqs. (6)-(7))
+ * on Yee grids with PEC walls, preconditioned by restricted additive Schwarz
+ * (Sec. II-B) whose subdomain solves are exact discrete-transform solves
+ * (Sec. III-A, Steps 1-3; Algorithm 1, exact_solve): forward DCT-II/DST-I
+ * transforms along x, y, z per staggered component, a closed-form 3x3 solve
+ * per wavenumber (eq. (12)), inverse transforms.
+ *
+ * Vector layout (every vector argument):
+ *   Device pointers to FP64 arrays.  One block per domain, concatenated at the
+ *   offsets returned by fmp_vector_layout.  Inside a domain of nx*ny*nz cells
+ *   the block is [3][nz][ny][nx] (components E_x, E_y, E_z; x fastest).
+ *   E_x sits at (i+1/2, j, k) in slot [k][j][i]; E_y at (i, j+1/2, k) in
+ *   [k][j][i]; E_z at (i, j, k+1/2) in [k][j][i].  Slot 0 along a component's
+ *   two node axes is the PEC wall: ignored on input, written as 0 on output.
+ *   The far wall node (index n) is not stored.
+ *
+ * Ownership: the caller owns every vector and every workspace.  A handle owns
+ *   small host-side plans only; its device tables live in the setup workspace,
+ *   which must stay allocated and untouched until fmp_destroy.  Nothing in
+ *   this library allocates device memory.
+ *
+ * Streams: `stream` is a hipStream_t passed as void* (NULL = the default
+ *   stream).  fmp_curlcurl_apply and fmp_apply_precond only enqueue work and
+ *   are safe to capture in a hipGraph; fmp_solve synchronises the stream for
+ *   its convergence checks.
+ *
+ * Errors: functions return an fmp_status; no exception crosses the ABI.  On a
+ *   negative status no output has been written unless stated.  The detail of
+ *   the last error on a handle is available from fmp_last_error.
+ *
+ * Threading: a handle is not thread safe; distinct handles are independent.
+ * Determinism: FP64 reductions use a fixed order, so results are bitwise
+ *   reproducible on one device for one configuration.
+ */
+#ifndef FLASHMP_H
+#define FLASHMP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fmp_ctx* fmp_handle;
+
+typedef enum {
+  FMP_OK = 0,
+  FMP_NOT_CONVERGED = 1,      /* result usable; see fmp_solve_info              */
+  FMP_ERR_INVALID_ARG = -1,   /* bad descriptor, size or null pointer           */
+  FMP_ERR_ALIAS = -2,         /* input and output vectors overlap               */
+  FMP_ERR_WORKSPACE = -3,     /* workspace missing, too small or misaligned     */
+  FMP_ERR_HIP = -4,           /* a HIP runtime call failed                       */
+  FMP_ERR_BREAKDOWN = -5,     /* Krylov breakdown or non-finite value           */
+  FMP_ERR_UNSUPPORTED = -6    /* valid request this build does not implement    */
+} fmp_status;
+
+typedef enum { FMP_FP64 = 0, FMP_FP32 = 1, FMP_BF16 = 2 } fmp_precision;
+
+/* One domain: a box of nx*ny*nz unit cells with PEC walls on all six faces.
+ * c = dt^2/(4 mu eps0 h^2) (the alpha of eq. (7) for eps_r = 1).
+ * eps_block: host array of relative permittivities, one per cube of
+ *   eps_block_size^3 cells, C order [nz/b][ny/b][nx/b]; NULL means eps_r = 1.
+ *   The permittivity at an E edge is the mean over the four cells sharing it.
+ * sub_x/y/z: owned subdomain side in cells (must divide the domain side;
+ *   0 = the whole axis, i.e. one box). */
+typedef struct {
+  int32_t nx, ny, nz;
+  double c;
+  const double* eps_block;
+  int32_t eps_block_size;
+  int32_t sub_x, sub_y, sub_z;
+} fmp_domain_desc;
+
+/* Preconditioner options.
+ * overlap: Schwarz overlap gamma in cells, >= 1 (boxes are clipped at walls).
+ * precision: arithmetic of the transforms and block solve (fmp_precision).
+ *   FP64 and FP32 run on the vector ALU; BF16 runs the transforms as MFMA
+ *   GEMMs on bf16 operands with FP32 accumulation.
+ * use_learned: 1 reserves room for a coarse-correction network
+ *   (fmp_set_coarse_model); it is applied only once weights are set.
+ * batch_boxes: boxes per pipeline batch (0 = automatic); smaller batches keep
+ *   the transform staging resident in the last-level cache. */
+typedef struct {
+  int32_t overlap;
+  int32_t precision;
+  int32_t use_learned;
+  int32_t batch_boxes;
+} fmp_precond_desc;
+
+/* Krylov options.  solver: 0 = BiCGSTAB, 1 = flexible GMRES(restart).
+ * rtol: stop when ||b - A x||_2 / ||b - A x0||_2 <= rtol (Sec. IV-A).
+ * precond: 0 = none (identity), 1 = FlashMP RAS (+ learned part if set).
+ * check_every: host convergence check period for BiCGSTAB (>= 1). */
+typedef struct {
+  int32_t solver;
+  int32_t restart;
+  int32_t max_iter;
+  double rtol;
+  int32_t precond;
+  int32_t check_every;
+} fmp_solve_opts;
+
+typedef struct {
+  int32_t iterations;          /* BiCGSTAB loops or FGMRES Arnoldi steps      */
+  int32_t n_precond;           /* preconditioner applies                      */
+  int32_t n_spmv;              /* operator applies                            */
+  int32_t used_fallback;       /* applies where the learned part was rejected */
+  double rel_residual_true;    /* ||b - A x|| / ||b - A x0|| recomputed       */
+  double t_total_ms;
+} fmp_solve_info;
+
+/* Build the subdomain plans for n_domains independent domains.
+ * Two-phase: with ws == NULL, writes the workspace size to *ws_bytes and
+ * returns FMP_OK with *out = NULL.  Then call again with a device buffer of
+ * at least *ws_bytes bytes (256-byte aligned) to get a handle in *out.
+ * Errors: FMP_ERR_INVALID_ARG (sizes < 2, overlap < 1, sub not dividing the
+ * side, eps table missing its block size), FMP_ERR_WORKSPACE.  A domain
+ * whose boxes exceed the largest compiled transform size (48 cells) still
+ * gets a handle: the stencil and unpreconditioned solves work, while
+ * fmp_apply_precond and preconditioned solves return FMP_ERR_UNSUPPORTED. */
+fmp_status fmp_setup_subdomains(const fmp_domain_desc* domains, int32_t n_domains,
+                                const fmp_precond_desc* pd, void* ws, size_t* ws_bytes,
+                                void* stream, fmp_handle* out);
+
+/* offsets[0..n_domains]: element offset of each domain block; offsets[n] = total. */
+fmp_status fmp_vector_layout(fmp_handle h, int64_t* offsets);
+
+/* y = A x (the double-curl stencil with the permittivity scaling; Sec. III-A
+ * double-curl matrix, eq. (7)).  x, y: device, fmp_vector_layout length,
+ * must not overlap (FMP_ERR_ALIAS). */
+fmp_status fmp_curlcurl_apply(fmp_handle h, const double* x, double* y, void* stream);
+
+/* z = M^{-1} r: RAS with exact transform solves of every box (Sec. II-B;
+ * Algorithm 1, exact_solve), plus the learned coarse correction when set.
+ * r, z: device, must not overlap. */
+fmp_status fmp_apply_precond(fmp_handle h, const double* r, double* z, void* stream);
+
+/* Workspace the solver needs for `opts` (bytes).  */
+fmp_status fmp_solve_workspace(fmp_handle h, const fmp_solve_opts* opts, size_t* bytes);
+
+/* Solve A x = b.  x holds the initial guess on entry and the solution on
+ * exit.  ws: device buffer of fmp_solve_workspace bytes.  Returns FMP_OK,
+ * FMP_NOT_CONVERGED (x = last iterate), or FMP_ERR_BREAKDOWN (x = last finite
+ * iterate).  info may be NULL. */
+fmp_status fmp_solve(fmp_handle h, const double* b, double* x, const fmp_solve_opts* opts,
+                     void* ws, size_t ws_bytes, fmp_solve_info* info, void* stream);
+
+/* ---- learned coarse correction (z += P0 MLP(R0 r)) --------------------------
+ * R0: mean of r over the unknowns each subdomain owns, per component; the
+ * coarse vector is [3][n_subdomains] (subdomains in the same order as the
+ * boxes: domain, then z, y, x).  The MLP maps the coarse residual scaled to
+ * unit norm through in -> hidden (ReLU) -> hidden (ReLU) -> in with bf16
+ * weights and FP32 accumulation; its output, times the norm, is injected
+ * piecewise-constantly (P0) into the owned unknowns. */
+
+/* Number of coarse unknowns (3 * subdomains) of a handle. */
+fmp_status fmp_coarse_size(fmp_handle h, int32_t* n_coarse);
+
+/* Host FP32 weights in order W1[hid][in], b1[hid], W2[hid][hid], b2[hid],
+ * W3[in][hid], b3[in]; bytes must equal 4*(2*in*hid + hid*hid + 2*hid + in).
+ * Weights are rounded to bf16 on upload (biases stay FP32).  hidden <= 512.
+ * Passing weights == NULL disables the correction. */
+fmp_status fmp_set_coarse_model(fmp_handle h, int32_t hidden, const float* weights, size_t bytes);
+
+/* rc = R0 r (device, FP64 out, fmp_coarse_size entries). */
+fmp_status fmp_coarse_restrict(fmp_handle h, const double* r, double* rc, void* stream);
+
+/* ---- MLP training kernels (used to fit the coarse model) -------------------
+ * All pointers are device FP32 unless noted.  Shapes: X [batch][in],
+ * Y [batch][in], params = the flat FP32 layout of fmp_set_coarse_model,
+ * grads same size.  fmp_mlp_loss_grad: forward with bf16 copies of the
+ * weights and FP32 accumulation, MSE loss mean over batch*in entries written
+ * to *loss_dev (device FP32), and its gradient with respect to params.
+ * fmp_mlp_adam: one Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on params
+ * with moments m, v (device FP32, zero initialised), step count t >= 1. */
+fmp_status fmp_mlp_loss_grad(int32_t in_dim, int32_t hidden, int32_t batch, const float* params,
+                             const float* X, const float* Y, float* grads, float* loss_dev,
+                             void* scratch, size_t scratch_bytes, void* stream);
+size_t fmp_mlp_scratch_bytes(int32_t in_dim, int32_t hidden, int32_t batch);
+fmp_status fmp_mlp_adam(int32_t n_params, float* params, const float* grads, float* m, float* v,
+                        int32_t t, float lr, void* stream);
+
+fmp_status fmp_destroy(fmp_handle h);
+const char* fmp_status_string(fmp_status st);
+const char* fmp_last_error(fmp_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FLASHMP_H */

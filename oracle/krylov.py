@@ -14,9 +14,12 @@ Readings
   variant (FGMRES, Saad 1993), which stores the preconditioned vectors Z and
   so stays correct when M^{-1} changes between iterations (reduced precision,
   learned correction).
-* BiCGSTAB is van der Vorst's 1992 algorithm.  When the recursive residual
-  meets the tolerance the true residual b - A x is recomputed; if it does not
-  meet it, the iteration restarts from the true residual.
+* BiCGSTAB is van der Vorst's 1992 algorithm, with the stopping test on the
+  residual r at the end of each full step (no exit half-way on s: since
+  omega minimises ||s - omega t||, ||r|| <= ||s|| and the step count is the
+  same).  When the recursive residual meets the tolerance the true residual
+  b - A x is recomputed; if it does not meet it, the iteration restarts from
+  the true residual.
 * Arnoldi uses classical Gram-Schmidt; a second CGS pass runs when the norm
   of w drops by more than a factor 10 in the first pass.
 * One iteration = one preconditioner apply + one SpMV for FGMRES, two of
@@ -68,12 +71,6 @@ def bicgstab(A, b, M=None, x0=None, tol=1e-8, maxiter=1000):
             alpha = rho / _dot(rhat, v)
             s = r - alpha * v
             it += 1
-            snorm = _nrm(s)
-            if snorm <= tol * r0:
-                x = x + alpha * phat
-                hist.append(snorm / r0)
-                restart = True
-                break
             shat = M(s)
             t = A(shat)
             tt = _dot(t, t)

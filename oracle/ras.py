@@ -114,3 +114,26 @@ def ras_apply_matrix(r_pad, c, sub, overlap=1, eps_cell=None):
         keep = own[idx]
         z[idx[keep]] = sol[keep]
     return yee.to_padded(z, nx, ny, nz)
+
+
+def ras_apply_subset(r_pad, c, sub, overlap, eps_cell, which):
+    """Owned output blocks of M_RAS^{-1} r for the subdomains listed in `which`.
+
+    Returns {index: (owned ranges, block (3, sz, sy, sx))}; used to check a
+    sample of subdomains of a grid too large for the full oracle.
+    """
+    _, nz, ny, nx = r_pad.shape
+    subs = subdomains(nx, ny, nz, sub, overlap)
+    out = {}
+    for idx in which:
+        s = subs[idx]
+        (ox0, ox1), (oy0, oy1), (oz0, oz1) = s["own"]
+        (bx0, bx1), (by0, by1), (bz0, bz1) = s["box"]
+        alpha = subdomain_alpha(c, eps_cell, s["own"])
+        box = np.array(r_pad[:, bz0:bz1, by0:by1, bx0:bx1], dtype=np.float64)
+        e = transforms.box_solve_transform(yee.from_padded(box), bx1 - bx0, by1 - by0,
+                                           bz1 - bz0, alpha)
+        ebox = yee.to_padded(e, bx1 - bx0, by1 - by0, bz1 - bz0)
+        out[idx] = (s["own"], ebox[:, oz0 - bz0:oz1 - bz0, oy0 - by0:oy1 - by0,
+                                   ox0 - bx0:ox1 - bx0])
+    return out

@@ -158,3 +158,31 @@ def apply_A_padded(v, c, eps_cell=None):
     _, nz, ny, nx = v.shape
     A = assemble_A(nx, ny, nz, c, eps_cell)
     return to_padded(A @ from_padded(v), nx, ny, nz)
+
+
+def apply_A_at(v, c, eps_cell, points):
+    """(A v) at selected padded slots, for checks on grids too large to assemble.
+
+    points: iterable of (q, k, j, i).  Each value comes from a window of up to
+    5 cells per axis around the slot, assembled as its own PEC domain whose
+    low faces start at least two cells before the slot; the stencil of the
+    centre slot reaches one cell, so it only sees window-interior values and
+    the result equals the global operator's.  A window face that coincides
+    with a global wall is that wall.
+    """
+    _, nz, ny, nx = v.shape
+    out = []
+    for (q, k, j, i) in points:
+        lo = [max(0, a - 2) for a in (i, j, k)]
+        hi = [min(n, a + 3) for a, n in zip((i, j, k), (nx, ny, nz))]
+        sub = v[:, lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]].copy()
+        wnx, wny, wnz = hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2]
+        # a window slot 0 that is not a global wall is an ordinary value the
+        # centre stencil never touches; zero it so the window is a valid input
+        sub[0, 0, :, :] = 0; sub[0, :, 0, :] = 0
+        sub[1, 0, :, :] = 0; sub[1, :, :, 0] = 0
+        sub[2, :, 0, :] = 0; sub[2, :, :, 0] = 0
+        ew = None if eps_cell is None else eps_cell[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]]
+        y = apply_A_padded(sub, c, ew)
+        out.append(y[q, k - lo[2], j - lo[1], i - lo[0]])
+    return np.array(out)

@@ -1,0 +1,158 @@
+"""Thin Python binding of the FlashMP C ABI (argument marshalling only).
+
+Every step of the solver runs inside libflashmp.so; PyTorch only provides
+device memory (workspaces, vectors) and the current stream.  Vectors are
+float64 CUDA tensors in the padded layout of include/flashmp.h.
+"""
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib
+
+
+class FlashMPError(RuntimeError):
+    def __init__(self, status, where, detail=""):
+        self.status = status
+        name = _lib.STATUS.get(status, str(status))
+        super().__init__(f"{where}: {name}{(' - ' + detail) if detail else ''}")
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+def _check(st, where, h=None, ok=(0,)):
+    if st in ok:
+        return st
+    detail = ""
+    if h is not None and h.value:
+        detail = _lib.load().fmp_last_error(h).decode()
+    raise FlashMPError(st, where, detail)
+
+
+def domain_desc(nx, ny, nz, c, eps=None, eps_block=0, sub=(0, 0, 0)):
+    """Build an fmp_domain_desc; `eps` is the (nz/b, ny/b, nx/b) permittivity table or None."""
+    d = _lib.DomainDesc()
+    d.nx, d.ny, d.nz, d.c = int(nx), int(ny), int(nz), float(c)
+    sub = (sub, sub, sub) if np.isscalar(sub) else tuple(sub)
+    d.sub_x, d.sub_y, d.sub_z = (int(s) for s in sub)
+    keep = None
+    if eps is not None:
+        keep = np.ascontiguousarray(eps, dtype=np.float64)
+        d.eps_block = keep.ctypes.data_as(C.POINTER(C.c_double))
+        d.eps_block_size = int(eps_block)
+    else:
+        d.eps_block = None
+        d.eps_block_size = 0
+    return d, keep
+
+
+class Handle:
+    """A set of domains with their RAS plans (fmp_setup_subdomains) and workspace."""
+
+    def __init__(self, domains, overlap=1, precision="fp64", use_learned=False, batch_boxes=0,
+                 device="cuda", stream=None):
+        L = _lib.load()
+        keep = []
+        arr = (_lib.DomainDesc * len(domains))()
+        for i, dom in enumerate(domains):
+            d, k = domain_desc(**dom)
+            arr[i] = d
+            keep.append(k)
+        pd = _lib.PrecondDesc(int(overlap), _lib.PRECISION[precision], int(bool(use_learned)),
+                              int(batch_boxes))
+        nbytes = C.c_size_t(0)
+        h = C.c_void_p()
+        s = _stream(stream)
+        _check(L.fmp_setup_subdomains(arr, len(domains), C.byref(pd), None, C.byref(nbytes), s,
+                                      C.byref(h)), "fmp_setup_subdomains(size)")
+        self.ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=device)
+        _check(L.fmp_setup_subdomains(arr, len(domains), C.byref(pd), _ptr(self.ws),
+                                      C.byref(nbytes), s, C.byref(h)), "fmp_setup_subdomains")
+        self.h = h
+        self.n_domains = len(domains)
+        self.precision = precision
+        self.device = device
+        offs = (C.c_int64 * (len(domains) + 1))()
+        _check(L.fmp_vector_layout(h, offs), "fmp_vector_layout", h)
+        self.offsets = [int(o) for o in offs]
+        self.length = self.offsets[-1]
+        self._solve_ws = None
+
+    def close(self):
+        if self.h is not None and self.h.value:
+            _lib.load().fmp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def new_vector(self):
+        return torch.zeros(self.length, dtype=torch.float64, device=self.device)
+
+    def curlcurl_apply(self, x, y, stream=None):
+        return fmp_curlcurl_apply(self, x, y, stream)
+
+    def apply_precond(self, r, z, stream=None):
+        return fmp_apply_precond(self, r, z, stream)
+
+    def solve(self, b, x, **kw):
+        return fmp_solve(self, b, x, **kw)
+
+
+def fmp_setup_subdomains(domains, **kw):
+    return Handle(domains, **kw)
+
+
+def fmp_curlcurl_apply(h, x, y, stream=None):
+    _check(_lib.load().fmp_curlcurl_apply(h.h, _ptr(x), _ptr(y), _stream(stream)),
+           "fmp_curlcurl_apply", h.h)
+
+
+def fmp_apply_precond(h, r, z, stream=None):
+    _check(_lib.load().fmp_apply_precond(h.h, _ptr(r), _ptr(z), _stream(stream)),
+           "fmp_apply_precond", h.h)
+
+
+def solve_opts(solver="fgmres", restart=30, max_iter=500, rtol=1e-8, precond=True, check_every=1):
+    return _lib.SolveOpts({"bicgstab": 0, "fgmres": 1}[solver], int(restart), int(max_iter),
+                          float(rtol), int(bool(precond)), int(check_every))
+
+
+def fmp_solve(h, b, x, stream=None, raise_on_breakdown=True, **kw):
+    """Solve A x = b in place of x; returns a dict with the solve statistics."""
+    L = _lib.load()
+    o = solve_opts(**kw)
+    nbytes = C.c_size_t(0)
+    _check(L.fmp_solve_workspace(h.h, C.byref(o), C.byref(nbytes)), "fmp_solve_workspace", h.h)
+    if h._solve_ws is None or h._solve_ws.numel() < nbytes.value:
+        h._solve_ws = None
+        h._solve_ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=h.device)
+    info = _lib.SolveInfo()
+    st = L.fmp_solve(h.h, _ptr(b), _ptr(x), C.byref(o), _ptr(h._solve_ws), nbytes.value,
+                     C.byref(info), _stream(stream))
+    ok = (0, 1) if raise_on_breakdown else (0, 1, -5)
+    _check(st, "fmp_solve", h.h, ok=ok)
+    return dict(status=_lib.STATUS[st], iterations=info.iterations, n_precond=info.n_precond,
+                n_spmv=info.n_spmv, used_fallback=info.used_fallback,
+                rel_residual_true=info.rel_residual_true, t_total_ms=info.t_total_ms)
+
+
+def release_solver_workspace(h):
+    h._solve_ws = None

@@ -1,0 +1,695 @@
+// C ABI, plans and Krylov drivers of the FlashMP library (host side).
+//
+// Setup (fmp_setup_subdomains) splits every domain into owned blocks, extends
+// each by the overlap into a PEC box clipped at the walls (the RAS boxes of
+// Sec. II-B), builds the DCT-II / DST-I tables of every distinct box side,
+// sorts boxes into transform size classes and cuts each class into batches
+// whose spectral staging fits the last-level cache.  All device tables live
+// in the caller's workspace.
+//
+// fmp_solve runs right-preconditioned BiCGSTAB or flexible GMRES(m) (the
+// solvers of Sec. IV-A) entirely on the device: vector updates, dots and
+// scalar recurrences are kernels; the host only reads a few scalars per
+// iteration for the stopping test and the small Hessenberg least-squares
+// problem.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <memory>
+
+#include "fmp_common.h"
+
+using namespace fmp;
+
+struct Launch {
+  int cls;
+  int a0, na;   // pass A / C work items
+  int b0, nb;   // pass B work items
+};
+
+struct fmp_ctx {
+  std::vector<DomainDev> doms;
+  std::vector<BoxDev> boxes;
+  std::vector<long long> offsets;
+  std::vector<Launch> launches;
+  int prec = 0;
+  int overlap = 1;
+  bool precond_ok = true;      // every box side has a compiled transform class
+  int nsub = 0;
+  long long len = 0;
+  int ntiles = 0;
+  // device regions inside the workspace
+  DomainDev* d_doms = nullptr;
+  BoxDev* d_boxes = nullptr;
+  StencilTile* d_tiles = nullptr;
+  double* d_eps = nullptr;
+  void* d_tab = nullptr;
+  float* d_sig32 = nullptr;
+  int4* d_work_a = nullptr;
+  int4* d_work_b = nullptr;
+  void* d_W = nullptr;
+  double* d_part = nullptr;
+  double* d_S = nullptr;
+  // learned coarse correction
+  bool use_learned = false;
+  bool learned_set = false;
+  int hidden = 0;
+  double* d_rc = nullptr;      // R0 r (3*nsub), then the scaled correction
+  void* d_mlp = nullptr;       // weights + activations
+  size_t mlp_bytes = 0;
+  double* h_S = nullptr;       // pinned host mirror of scalars
+  std::string err;
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+constexpr int kScal = 256;      // doubles in the scalar area
+constexpr int kScalH = 16;      // h column of FGMRES
+constexpr int kScalW = 64;      // ||w||^2
+constexpr int kScalY = 128;     // FGMRES update coefficients
+
+struct Parts {
+  int own0, own1, box0, box1;
+};
+
+std::vector<Parts> axis_parts(int n, int sub, int overlap) {
+  std::vector<Parts> out;
+  if (sub <= 0) sub = n;
+  for (int a = 0; a < n; a += sub)
+    out.push_back({a, a + sub, std::max(0, a - overlap), std::min(n, a + sub + overlap)});
+  return out;
+}
+
+int class_of(int n) {
+  for (int c = 0; c < kNumClasses; ++c)
+    if (kClasses[c] >= n) return c;
+  return -1;
+}
+
+// Orthonormal DCT-II (rows p, columns l) and DST-I embedded in an n x n
+// block (row/column 0 zero), both stored with row stride kTS; sigma_m.
+void basis_tables(int n, std::vector<double>& dct, std::vector<double>& dst,
+                  std::vector<double>& sig) {
+  dct.assign(kTS * kTS, 0.0);
+  dst.assign(kTS * kTS, 0.0);
+  sig.assign(kTS, 0.0);
+  const double sc = sqrt(2.0 / n);
+  for (int p = 0; p < n; ++p)
+    for (int l = 0; l < n; ++l) {
+      // cos(pi p (2l+1) / (2n)) with the integer angle reduced mod 4n
+      const long a = (long)p * (2 * l + 1) % (4L * n);
+      double v = sc * cos(M_PI * (double)a / (2.0 * n));
+      if (p == 0) v = 1.0 / sqrt((double)n);
+      dct[p * kTS + l] = v;
+    }
+  for (int m = 1; m < n; ++m)
+    for (int l = 1; l < n; ++l) {
+      const long a = (long)m * l % (2L * n);
+      dst[m * kTS + l] = sc * sin(M_PI * (double)a / (double)n);
+    }
+  for (int m = 0; m < n; ++m) sig[m] = 2.0 * sin(M_PI * m / (2.0 * n));
+}
+
+bool overlaps(const void* a, const void* b, long long bytes) {
+  const char* pa = (const char*)a;
+  const char* pb = (const char*)b;
+  return pa < pb + bytes && pb < pa + bytes;
+}
+
+fmp_status hip_fail(fmp_ctx* h, hipError_t e, const char* what) {
+  if (h) h->err = std::string(what) + ": " + hipGetErrorString(e);
+  return FMP_ERR_HIP;
+}
+
+#define HIPCHK(h, call)                                  \
+  do {                                                   \
+    hipError_t _e = (call);                              \
+    if (_e != hipSuccess) return hip_fail(h, _e, #call); \
+  } while (0)
+
+uint16_t to_bf16(double x) {
+  float f = (float)x;
+  uint32_t u;
+  memcpy(&u, &f, 4);
+  const uint32_t lsb = (u >> 16) & 1u;
+  u += 0x7fffu + lsb;   // round to nearest even
+  return (uint16_t)(u >> 16);
+}
+
+}  // namespace
+
+// ============================================================== precond / spmv
+static fmp_status precond_apply(fmp_ctx* h, const double* r, double* z, hipStream_t s,
+                                const double* coarse) {
+  const int prec = h->prec;
+  for (const Launch& L : h->launches) {
+    if (prec == FMP_BF16) {
+      HIPCHK(h, launch_mfma_pass_a(L.cls, r, (float*)h->d_W, h->d_boxes, h->d_doms,
+                                   h->d_work_a + L.a0, L.na, (const __hip_bfloat16*)h->d_tab, s));
+      HIPCHK(h, launch_mfma_pass_b(L.cls, (float*)h->d_W, h->d_boxes, h->d_work_b + L.b0, L.nb,
+                                   (const __hip_bfloat16*)h->d_tab, h->d_sig32, s));
+      HIPCHK(h, launch_mfma_pass_c(L.cls, (const float*)h->d_W, z, h->d_boxes, h->d_doms,
+                                   h->d_work_a + L.a0, L.na, (const __hip_bfloat16*)h->d_tab,
+                                   coarse, h->nsub, s));
+    } else {
+      HIPCHK(h, launch_pass_a(prec, L.cls, r, h->d_W, h->d_boxes, h->d_doms, h->d_work_a + L.a0,
+                              L.na, h->d_tab, s));
+      HIPCHK(h, launch_pass_b(prec, L.cls, h->d_W, h->d_boxes, h->d_work_b + L.b0, L.nb,
+                              h->d_tab, s));
+      HIPCHK(h, launch_pass_c(prec, L.cls, h->d_W, z, h->d_boxes, h->d_doms, h->d_work_a + L.a0,
+                              L.na, h->d_tab, coarse, h->nsub, s));
+    }
+  }
+  return FMP_OK;
+}
+
+static fmp_status spmv(fmp_ctx* h, const double* x, double* y, hipStream_t s) {
+  HIPCHK(h, launch_curlcurl(x, y, h->d_doms, h->d_tiles, h->ntiles, h->d_eps, s));
+  return FMP_OK;
+}
+
+// Learned part: defined in fmp_coarse.hip (returns the device correction
+// vector to add in pass C, or nullptr when the model is not set).
+fmp_status fmp_coarse_forward(fmp_ctx* h, const double* r, hipStream_t s, const double** out);
+size_t fmp_coarse_workspace(int nsub, int hidden_max);
+void fmp_coarse_bind(fmp_ctx* h, void* base);
+
+extern "C" {
+
+const char* fmp_status_string(fmp_status st) {
+  switch (st) {
+    case FMP_OK: return "ok";
+    case FMP_NOT_CONVERGED: return "not converged";
+    case FMP_ERR_INVALID_ARG: return "invalid argument";
+    case FMP_ERR_ALIAS: return "input and output overlap";
+    case FMP_ERR_WORKSPACE: return "workspace missing or too small";
+    case FMP_ERR_HIP: return "HIP runtime error";
+    case FMP_ERR_BREAKDOWN: return "Krylov breakdown or non-finite value";
+    case FMP_ERR_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+const char* fmp_last_error(fmp_handle h) { return h ? h->err.c_str() : "null handle"; }
+
+fmp_status fmp_setup_subdomains(const fmp_domain_desc* domains, int32_t n_domains,
+                                const fmp_precond_desc* pd, void* ws, size_t* ws_bytes,
+                                void* stream, fmp_handle* out) {
+  if (!domains || n_domains < 1 || !pd || !ws_bytes) return FMP_ERR_INVALID_ARG;
+  if (pd->overlap < 1) return FMP_ERR_INVALID_ARG;
+  if (pd->precision < FMP_FP64 || pd->precision > FMP_BF16) return FMP_ERR_INVALID_ARG;
+  if (out) *out = nullptr;
+  std::unique_ptr<fmp_ctx> h(new fmp_ctx());
+  h->prec = pd->precision;
+  h->overlap = pd->overlap;
+  h->use_learned = pd->use_learned != 0;
+
+  // ---- domains, boxes, eps tables
+  std::vector<double> eps_all;
+  long long off = 0;
+  std::vector<int> sides_used(kMaxSide + 1, 0);
+  for (int d = 0; d < n_domains; ++d) {
+    const fmp_domain_desc& D = domains[d];
+    if (D.nx < 2 || D.ny < 2 || D.nz < 2 || !(D.c >= 0.0) || !isfinite(D.c))
+      return FMP_ERR_INVALID_ARG;
+    const int sub[3] = {D.sub_x > 0 ? D.sub_x : D.nx, D.sub_y > 0 ? D.sub_y : D.ny,
+                        D.sub_z > 0 ? D.sub_z : D.nz};
+    const int nn[3] = {D.nx, D.ny, D.nz};
+    for (int a = 0; a < 3; ++a)
+      if (sub[a] < 1 || nn[a] % sub[a]) return FMP_ERR_INVALID_ARG;
+    DomainDev dd{};
+    dd.nx = D.nx; dd.ny = D.ny; dd.nz = D.nz;
+    dd.offset = off;
+    dd.c = D.c;
+    dd.eps_b = 0;
+    int nbx = 0, nby = 0, nbz = 0;
+    if (D.eps_block) {
+      const int b = D.eps_block_size;
+      if (b < 1) return FMP_ERR_INVALID_ARG;
+      nbx = (D.nx + b - 1) / b; nby = (D.ny + b - 1) / b; nbz = (D.nz + b - 1) / b;
+      dd.eps_b = b;
+      dd.eps_off = (int)eps_all.size();
+      dd.eps_nbx = nbx; dd.eps_nby = nby; dd.eps_nbz = nbz;
+      for (long long i = 0; i < (long long)nbx * nby * nbz; ++i) {
+        const double e = D.eps_block[i];
+        if (!(e > 0.0) || !isfinite(e)) return FMP_ERR_INVALID_ARG;
+        eps_all.push_back(e);
+      }
+    }
+    h->doms.push_back(dd);
+    h->offsets.push_back(off);
+    off += 3LL * D.nx * D.ny * D.nz;
+
+    const auto px = axis_parts(D.nx, sub[0], pd->overlap);
+    const auto py = axis_parts(D.ny, sub[1], pd->overlap);
+    const auto pz = axis_parts(D.nz, sub[2], pd->overlap);
+    for (const Parts& Z : pz)
+      for (const Parts& Y : py)
+        for (const Parts& X : px) {
+          BoxDev B{};
+          B.dom = d;
+          B.bx0 = X.box0; B.by0 = Y.box0; B.bz0 = Z.box0;
+          B.nx = X.box1 - X.box0; B.ny = Y.box1 - Y.box0; B.nz = Z.box1 - Z.box0;
+          B.ox0 = X.own0; B.oy0 = Y.own0; B.oz0 = Z.own0;
+          B.sx = X.own1 - X.own0; B.sy = Y.own1 - Y.own0; B.sz = Z.own1 - Z.own0;
+          B.sub = h->nsub++;
+          B.vol = (long long)B.nx * B.ny * B.nz;
+          if (std::min(B.nx, std::min(B.ny, B.nz)) < 2) return FMP_ERR_INVALID_ARG;
+          if (std::max(B.nx, std::max(B.ny, B.nz)) > kMaxSide) h->precond_ok = false;
+          else sides_used[B.nx] = sides_used[B.ny] = sides_used[B.nz] = 1;
+          // alpha = c / mean eps over the owned cells
+          double alpha = D.c;
+          if (D.eps_block) {
+            long double acc = 0.0L;
+            const int b = D.eps_block_size;
+            for (int k = Z.own0; k < Z.own1; ++k)
+              for (int j = Y.own0; j < Y.own1; ++j)
+                for (int i = X.own0; i < X.own1; ++i)
+                  acc += D.eps_block[((long long)(k / b) * nby + j / b) * nbx + i / b];
+            const double mean = (double)(acc / ((long double)B.sx * B.sy * B.sz));
+            alpha = D.c / mean;
+          }
+          B.alpha = alpha;
+          h->boxes.push_back(B);
+        }
+  }
+  h->offsets.push_back(off);
+  h->len = off;
+
+  // ---- transform tables for each side in use
+  std::vector<int> side_slot(kMaxSide + 1, -1);
+  int nsides = 0;
+  for (int n = 2; n <= kMaxSide; ++n)
+    if (sides_used[n]) side_slot[n] = nsides++;
+  const long long per_side = 2LL * kTS * kTS + kTS;   // dct, dst, sig
+  std::vector<double> tab64((size_t)(per_side * nsides), 0.0);
+  {
+    std::vector<double> c, s, g;
+    for (int n = 2; n <= kMaxSide; ++n) {
+      if (side_slot[n] < 0) continue;
+      basis_tables(n, c, s, g);
+      double* base = tab64.data() + side_slot[n] * per_side;
+      std::copy(c.begin(), c.end(), base);
+      std::copy(s.begin(), s.end(), base + kTS * kTS);
+      std::copy(g.begin(), g.end(), base + 2 * kTS * kTS);
+    }
+  }
+  if (!h->precond_ok) h->boxes.clear();   // stencil and unpreconditioned solves only
+  for (BoxDev& B : h->boxes) {
+    const int sides[3] = {B.nx, B.ny, B.nz};
+    for (int a = 0; a < 3; ++a) {
+      const int base = (int)(side_slot[sides[a]] * per_side);
+      B.dct[a] = base;
+      B.dst[a] = base + kTS * kTS;
+      B.sig[a] = base + 2 * kTS * kTS;
+    }
+  }
+
+  // ---- size classes and batches
+  int batch = pd->batch_boxes;
+  if (batch <= 0) batch = (h->prec == FMP_FP64) ? 128 : 256;
+  std::vector<int> order(h->boxes.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+  std::vector<int> cls(h->boxes.size());
+  for (size_t i = 0; i < h->boxes.size(); ++i) {
+    const BoxDev& B = h->boxes[i];
+    cls[i] = class_of(std::max(B.nx, std::max(B.ny, B.nz)));
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cls[a] < cls[b]; });
+  std::vector<int4> work_a, work_b;
+  long long w_batch_max = 0;
+  for (size_t i0 = 0; i0 < order.size();) {
+    const int c = cls[order[i0]];
+    size_t i1 = i0;
+    while (i1 < order.size() && cls[order[i1]] == c && (int)(i1 - i0) < batch) ++i1;
+    Launch L{c, (int)work_a.size(), 0, (int)work_b.size(), 0};
+    const int zs = (h->prec == FMP_BF16) ? mfma_zslab(c) : pass_a_zslab(c);
+    long long woff = 0;
+    for (size_t i = i0; i < i1; ++i) {
+      BoxDev& B = h->boxes[order[i]];
+      B.w_off = woff;                 // staging is reused batch after batch
+      woff += 3 * B.vol;
+      for (int q = 0; q < 3; ++q)
+        for (int z0 = 0; z0 < B.nz; z0 += zs) work_a.push_back(make_int4(order[i], q, z0, 0));
+      for (int c0 = 0; c0 < B.nx * B.ny; c0 += 64) work_b.push_back(make_int4(order[i], c0, 0, 0));
+    }
+    w_batch_max = std::max(w_batch_max, woff);
+    L.na = (int)work_a.size() - L.a0;
+    L.nb = (int)work_b.size() - L.b0;
+    h->launches.push_back(L);
+    i0 = i1;
+  }
+
+  // ---- stencil tiles
+  std::vector<StencilTile> tiles;
+  for (int d = 0; d < n_domains; ++d) {
+    const DomainDev& D = h->doms[d];
+    for (int z0 = 0; z0 < D.nz; z0 += kStencilZC)
+      for (int y0 = 0; y0 < D.ny; y0 += kStencilTY)
+        for (int x0 = 0; x0 < D.nx; x0 += kStencilTX) tiles.push_back({d, x0, y0, z0});
+  }
+  h->ntiles = (int)tiles.size();
+
+  // ---- workspace layout
+  const size_t tsz = (h->prec == FMP_FP64) ? 8 : (h->prec == FMP_FP32 ? 4 : 2);
+  const size_t wsz = (h->prec == FMP_FP64) ? 8 : 4;
+  size_t cur = 0;
+  const size_t o_doms = cur; cur = align_up(cur + h->doms.size() * sizeof(DomainDev));
+  const size_t o_boxes = cur; cur = align_up(cur + h->boxes.size() * sizeof(BoxDev));
+  const size_t o_tiles = cur; cur = align_up(cur + tiles.size() * sizeof(StencilTile));
+  const size_t o_eps = cur; cur = align_up(cur + std::max<size_t>(1, eps_all.size()) * 8);
+  const size_t o_tab = cur; cur = align_up(cur + tab64.size() * tsz);
+  const size_t o_sig32 = cur; cur = align_up(cur + tab64.size() * 4);
+  const size_t o_wa = cur; cur = align_up(cur + work_a.size() * sizeof(int4));
+  const size_t o_wb = cur; cur = align_up(cur + work_b.size() * sizeof(int4));
+  const size_t o_part = cur; cur = align_up(cur + (size_t)kMaxDots * kRedBlocks * 8);
+  const size_t o_S = cur; cur = align_up(cur + kScal * 8);
+  const size_t o_learn = cur;
+  if (h->use_learned) cur = align_up(cur + fmp_coarse_workspace(h->nsub, 512));
+  const size_t o_W = cur; cur = align_up(cur + (size_t)w_batch_max * wsz);
+  const size_t need = cur;
+
+  if (!ws) {
+    *ws_bytes = need;
+    return FMP_OK;
+  }
+  if (*ws_bytes < need) return FMP_ERR_WORKSPACE;
+  if (((uintptr_t)ws) % kAlign) return FMP_ERR_WORKSPACE;
+  if (!out) return FMP_ERR_INVALID_ARG;
+  char* base = (char*)ws;
+  h->d_doms = (DomainDev*)(base + o_doms);
+  h->d_boxes = (BoxDev*)(base + o_boxes);
+  h->d_tiles = (StencilTile*)(base + o_tiles);
+  h->d_eps = (double*)(base + o_eps);
+  h->d_tab = base + o_tab;
+  h->d_sig32 = (float*)(base + o_sig32);
+  h->d_work_a = (int4*)(base + o_wa);
+  h->d_work_b = (int4*)(base + o_wb);
+  h->d_part = (double*)(base + o_part);
+  h->d_S = (double*)(base + o_S);
+  h->d_W = base + o_W;
+  if (h->use_learned) fmp_coarse_bind(h.get(), base + o_learn);
+
+  // typed tables
+  std::vector<char> tabbytes(tab64.size() * tsz);
+  std::vector<float> sig32(tab64.size());
+  for (size_t i = 0; i < tab64.size(); ++i) {
+    sig32[i] = (float)tab64[i];
+    if (h->prec == FMP_FP64) memcpy(&tabbytes[i * 8], &tab64[i], 8);
+    else if (h->prec == FMP_FP32) { float f = (float)tab64[i]; memcpy(&tabbytes[i * 4], &f, 4); }
+    else { uint16_t b = to_bf16(tab64[i]); memcpy(&tabbytes[i * 2], &b, 2); }
+  }
+  hipStream_t s = (hipStream_t)stream;
+  fmp_ctx* hp = h.get();
+  HIPCHK(hp, hipMemcpyAsync(h->d_doms, h->doms.data(), h->doms.size() * sizeof(DomainDev),
+                            hipMemcpyHostToDevice, s));
+  HIPCHK(hp, hipMemcpyAsync(h->d_boxes, h->boxes.data(), h->boxes.size() * sizeof(BoxDev),
+                            hipMemcpyHostToDevice, s));
+  HIPCHK(hp, hipMemcpyAsync(h->d_tiles, tiles.data(), tiles.size() * sizeof(StencilTile),
+                            hipMemcpyHostToDevice, s));
+  if (!eps_all.empty())
+    HIPCHK(hp, hipMemcpyAsync(h->d_eps, eps_all.data(), eps_all.size() * 8, hipMemcpyHostToDevice, s));
+  HIPCHK(hp, hipMemcpyAsync(h->d_tab, tabbytes.data(), tabbytes.size(), hipMemcpyHostToDevice, s));
+  HIPCHK(hp, hipMemcpyAsync(h->d_sig32, sig32.data(), sig32.size() * 4, hipMemcpyHostToDevice, s));
+  HIPCHK(hp, hipMemcpyAsync(h->d_work_a, work_a.data(), work_a.size() * sizeof(int4),
+                            hipMemcpyHostToDevice, s));
+  HIPCHK(hp, hipMemcpyAsync(h->d_work_b, work_b.data(), work_b.size() * sizeof(int4),
+                            hipMemcpyHostToDevice, s));
+  HIPCHK(hp, hipHostMalloc((void**)&h->h_S, kScal * 8, hipHostMallocDefault));
+  HIPCHK(hp, hipStreamSynchronize(s));   // host staging vectors go out of scope
+  *out = h.release();
+  return FMP_OK;
+}
+
+fmp_status fmp_vector_layout(fmp_handle h, int64_t* offsets) {
+  if (!h || !offsets) return FMP_ERR_INVALID_ARG;
+  for (size_t i = 0; i < h->offsets.size(); ++i) offsets[i] = h->offsets[i];
+  return FMP_OK;
+}
+
+fmp_status fmp_destroy(fmp_handle h) {
+  if (!h) return FMP_ERR_INVALID_ARG;
+  if (h->h_S) (void)hipHostFree(h->h_S);
+  delete h;
+  return FMP_OK;
+}
+
+fmp_status fmp_curlcurl_apply(fmp_handle h, const double* x, double* y, void* stream) {
+  if (!h || !x || !y) return FMP_ERR_INVALID_ARG;
+  if (overlaps(x, y, h->len * 8)) return FMP_ERR_ALIAS;
+  return spmv(h, x, y, (hipStream_t)stream);
+}
+
+fmp_status fmp_apply_precond(fmp_handle h, const double* r, double* z, void* stream) {
+  if (!h || !r || !z) return FMP_ERR_INVALID_ARG;
+  if (overlaps(r, z, h->len * 8)) return FMP_ERR_ALIAS;
+  if (!h->precond_ok) {
+    h->err = "a box side exceeds the largest compiled transform size (48)";
+    return FMP_ERR_UNSUPPORTED;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const double* coarse = nullptr;
+  if (h->learned_set) {
+    fmp_status st = fmp_coarse_forward(h, r, s, &coarse);
+    if (st != FMP_OK) return st;
+  }
+  return precond_apply(h, r, z, s, coarse);
+}
+
+fmp_status fmp_solve_workspace(fmp_handle h, const fmp_solve_opts* o, size_t* bytes) {
+  if (!h || !o || !bytes) return FMP_ERR_INVALID_ARG;
+  const size_t vb = align_up((size_t)h->len * 8);
+  if (o->solver == 0) *bytes = 8 * vb;
+  else if (o->solver == 1) {
+    if (o->restart < 1 || o->restart > 32) return FMP_ERR_INVALID_ARG;
+    *bytes = (2 * (size_t)o->restart + 1) * vb;
+  } else return FMP_ERR_INVALID_ARG;
+  return FMP_OK;
+}
+
+}  // extern "C"
+
+// ============================================================== solvers
+namespace {
+
+struct Ctx {
+  fmp_ctx* h;
+  hipStream_t s;
+  const fmp_solve_opts* o;
+  fmp_solve_info* info;
+};
+
+fmp_status M(Ctx& c, const double* r, double* z) {
+  c.info->n_precond++;
+  if (c.o->precond == 0) {
+    HIPCHK(c.h, launch_scale_copy(r, 1.0, z, c.h->len, c.s));
+    return FMP_OK;
+  }
+  const double* coarse = nullptr;
+  if (c.h->learned_set) {
+    fmp_status st = fmp_coarse_forward(c.h, r, c.s, &coarse);
+    if (st != FMP_OK) return st;
+  }
+  return precond_apply(c.h, r, z, c.s, coarse);
+}
+
+fmp_status A(Ctx& c, const double* x, double* y) {
+  c.info->n_spmv++;
+  return spmv(c.h, x, y, c.s);
+}
+
+// r = b - A x into r (tmp used for A x), returns ||r||^2 through the host mirror
+fmp_status residual(Ctx& c, const double* b, const double* x, double* r, double* tmp,
+                    double* rr) {
+  fmp_status st = A(c, x, tmp);
+  if (st) return st;
+  fmp_ctx* h = c.h;
+  HIPCHK(h, launch_sub_norm(b, tmp, r, h->len, h->d_part, c.s));
+  HIPCHK(h, launch_reduce(h->d_part, 1, h->d_S + 7, 0, h->d_S, c.s));
+  HIPCHK(h, hipMemcpyAsync(h->h_S + 7, h->d_S + 7, 8, hipMemcpyDeviceToHost, c.s));
+  HIPCHK(h, hipStreamSynchronize(c.s));
+  *rr = h->h_S[7];
+  return FMP_OK;
+}
+
+fmp_status bicgstab(Ctx& c, const double* b, double* x, double* ws) {
+  fmp_ctx* h = c.h;
+  const long long n = h->len;
+  const size_t vb = align_up((size_t)n * 8) / 8;
+  double *r = ws, *rhat = ws + vb, *p = ws + 2 * vb, *v = ws + 3 * vb, *phat = ws + 4 * vb,
+         *sv = ws + 5 * vb, *shat = ws + 6 * vb, *t = ws + 7 * vb;
+  const double tol = c.o->rtol;
+  const int check = std::max(1, c.o->check_every);
+  double rr;
+  fmp_status st = residual(c, b, x, r, t, &rr);
+  if (st) return st;
+  if (!isfinite(rr)) return FMP_ERR_BREAKDOWN;
+  const double r0 = sqrt(rr);
+  c.info->rel_residual_true = 0.0;
+  if (r0 == 0.0) return FMP_OK;
+  int it = 0;
+  bool broke = false;
+  while (it < c.o->max_iter) {
+    HIPCHK(h, hipMemcpyAsync(rhat, r, n * 8, hipMemcpyDeviceToDevice, c.s));
+    HIPCHK(h, hipMemsetAsync(p, 0, n * 8, c.s));
+    HIPCHK(h, hipMemsetAsync(v, 0, n * 8, c.s));
+    double* hs = h->h_S;
+    hs[0] = rr; hs[1] = 1.0; hs[2] = 1.0; hs[3] = 1.0; hs[8] = 0.0;
+    HIPCHK(h, hipMemcpyAsync(h->d_S, hs, 9 * 8, hipMemcpyHostToDevice, c.s));
+    bool restart = false;
+    while (it < c.o->max_iter) {
+      HIPCHK(h, launch_bicg_p(r, p, v, h->d_S, n, c.s));
+      if ((st = M(c, p, phat))) return st;
+      if ((st = A(c, phat, v))) return st;
+      DotPtrs d1{};
+      d1.a[0] = rhat; d1.b[0] = v;
+      HIPCHK(h, launch_dots(d1, 1, n, h->d_part, c.s));
+      HIPCHK(h, launch_reduce(h->d_part, 1, h->d_S + 4, 1, h->d_S, c.s));
+      HIPCHK(h, launch_bicg_s(r, v, sv, h->d_S, n, c.s));
+      if ((st = M(c, sv, shat))) return st;
+      if ((st = A(c, shat, t))) return st;
+      DotPtrs d2{};
+      d2.a[0] = t; d2.b[0] = sv; d2.a[1] = t; d2.b[1] = t;
+      HIPCHK(h, launch_dots(d2, 2, n, h->d_part, c.s));
+      HIPCHK(h, launch_reduce(h->d_part, 2, h->d_S + 5, 2, h->d_S, c.s));
+      HIPCHK(h, launch_bicg_xr(x, phat, shat, sv, t, r, rhat, h->d_S, n, h->d_part, c.s));
+      HIPCHK(h, launch_reduce(h->d_part, 2, h->d_S + 7, 3, h->d_S, c.s));
+      ++it;
+      if (it % check == 0 || it >= c.o->max_iter) {
+        HIPCHK(h, hipMemcpyAsync(hs, h->d_S, 9 * 8, hipMemcpyDeviceToHost, c.s));
+        HIPCHK(h, hipStreamSynchronize(c.s));
+        const double rn = sqrt(hs[7]);
+        if (!isfinite(rn) || !isfinite(hs[0])) { broke = true; break; }
+        if (rn <= tol * r0) { restart = true; break; }
+        if (hs[3] == 0.0 || hs[0] == 0.0) { broke = true; break; }
+      }
+    }
+    if ((st = residual(c, b, x, r, t, &rr))) return st;
+    c.info->rel_residual_true = sqrt(rr) / r0;
+    if (!isfinite(rr)) broke = true;
+    if (!broke && sqrt(rr) <= tol * r0) { c.info->iterations = it; return FMP_OK; }
+    if (broke || !restart) break;
+  }
+  c.info->iterations = it;
+  return broke ? FMP_ERR_BREAKDOWN : FMP_NOT_CONVERGED;
+}
+
+fmp_status fgmres(Ctx& c, const double* b, double* x, double* ws) {
+  fmp_ctx* h = c.h;
+  const long long n = h->len;
+  const int m = c.o->restart;
+  const size_t vb = align_up((size_t)n * 8) / 8;
+  double* V = ws;
+  double* Z = ws + (size_t)(m + 1) * vb;
+  const double tol = c.o->rtol;
+  double* hs = h->h_S;
+  double beta2;
+  fmp_status st = residual(c, b, x, V, Z, &beta2);
+  if (st) return st;
+  if (!isfinite(beta2)) return FMP_ERR_BREAKDOWN;
+  double beta = sqrt(beta2);
+  const double r0 = beta;
+  c.info->rel_residual_true = 0.0;
+  if (r0 == 0.0) return FMP_OK;
+  int it = 0;
+  std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  while (it < c.o->max_iter) {
+    HIPCHK(h, launch_scale_copy(V, 1.0 / beta, V, n, c.s));
+    std::fill(H.begin(), H.end(), 0.0);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int ncols = 0;
+    for (int j = 0; j < m; ++j) {
+      double* vj = V + (size_t)j * vb;
+      double* zj = Z + (size_t)j * vb;
+      double* w = V + (size_t)(j + 1) * vb;
+      if ((st = M(c, vj, zj))) return st;
+      if ((st = A(c, zj, w))) return st;
+      // classical Gram-Schmidt: h = V^T w (and ||w||^2), w -= V h, ||w||^2
+      HIPCHK(h, launch_mdot(V, (long long)vb, j + 1, w, n, h->d_part, c.s));
+      HIPCHK(h, launch_reduce(h->d_part, j + 2, h->d_S + kScalH, 0, h->d_S, c.s));
+      HIPCHK(h, launch_mupdate(V, (long long)vb, j + 1, h->d_S + kScalH, w, n, h->d_part, c.s));
+      HIPCHK(h, launch_reduce(h->d_part, 1, h->d_S + kScalW, 0, h->d_S, c.s));
+      HIPCHK(h, hipMemcpyAsync(hs, h->d_S, kScal * 8, hipMemcpyDeviceToHost, c.s));
+      HIPCHK(h, hipStreamSynchronize(c.s));
+      std::vector<double> hcol(hs + kScalH, hs + kScalH + j + 1);
+      const double wn0 = sqrt(hs[kScalH + j + 1]);
+      double hn = sqrt(hs[kScalW]);
+      if (hn < 0.1 * wn0) {   // second CGS pass
+        HIPCHK(h, launch_mdot(V, (long long)vb, j + 1, w, n, h->d_part, c.s));
+        HIPCHK(h, launch_reduce(h->d_part, j + 2, h->d_S + kScalH, 0, h->d_S, c.s));
+        HIPCHK(h, launch_mupdate(V, (long long)vb, j + 1, h->d_S + kScalH, w, n, h->d_part, c.s));
+        HIPCHK(h, launch_reduce(h->d_part, 1, h->d_S + kScalW, 0, h->d_S, c.s));
+        HIPCHK(h, hipMemcpyAsync(hs, h->d_S, kScal * 8, hipMemcpyDeviceToHost, c.s));
+        HIPCHK(h, hipStreamSynchronize(c.s));
+        for (int i = 0; i <= j; ++i) hcol[i] += hs[kScalH + i];
+        hn = sqrt(hs[kScalW]);
+      }
+      if (!isfinite(hn)) return FMP_ERR_BREAKDOWN;
+      for (int i = 0; i <= j; ++i) H[i * m + j] = hcol[i];
+      H[(j + 1) * m + j] = hn;
+      for (int i = 0; i < j; ++i) {
+        const double a = H[i * m + j], bb = H[(i + 1) * m + j];
+        H[i * m + j] = cs[i] * a + sn[i] * bb;
+        H[(i + 1) * m + j] = -sn[i] * a + cs[i] * bb;
+      }
+      const double a = H[j * m + j], bb = H[(j + 1) * m + j];
+      const double den = hypot(a, bb);
+      cs[j] = den == 0.0 ? 1.0 : a / den;
+      sn[j] = den == 0.0 ? 0.0 : bb / den;
+      H[j * m + j] = cs[j] * a + sn[j] * bb;
+      H[(j + 1) * m + j] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      ++it;
+      ncols = j + 1;
+      if (hn == 0.0 || fabs(g[j + 1]) <= tol * r0 || it >= c.o->max_iter) break;
+      HIPCHK(h, launch_scale_copy(w, 1.0 / hn, w, n, c.s));
+    }
+    // back substitution of the triangular least-squares system
+    for (int i = ncols - 1; i >= 0; --i) {
+      double acc = g[i];
+      for (int k = i + 1; k < ncols; ++k) acc -= H[i * m + k] * y[k];
+      y[i] = acc / H[i * m + i];
+    }
+    for (int i = 0; i < ncols; ++i) hs[kScalY + i] = y[i];
+    HIPCHK(h, hipMemcpyAsync(h->d_S + kScalY, hs + kScalY, ncols * 8, hipMemcpyHostToDevice, c.s));
+    HIPCHK(h, launch_xupdate(Z, (long long)vb, ncols, h->d_S + kScalY, x, n, c.s));
+    if ((st = residual(c, b, x, V, Z, &beta2))) return st;
+    beta = sqrt(beta2);
+    c.info->rel_residual_true = beta / r0;
+    if (!isfinite(beta)) return FMP_ERR_BREAKDOWN;
+    if (beta <= tol * r0) { c.info->iterations = it; return FMP_OK; }
+  }
+  c.info->iterations = it;
+  return FMP_NOT_CONVERGED;
+}
+
+}  // namespace
+
+extern "C" fmp_status fmp_solve(fmp_handle h, const double* b, double* x, const fmp_solve_opts* o,
+                                void* ws, size_t ws_bytes, fmp_solve_info* info, void* stream) {
+  if (!h || !b || !x || !o || !ws) return FMP_ERR_INVALID_ARG;
+  if (o->max_iter < 1 || !(o->rtol > 0.0)) return FMP_ERR_INVALID_ARG;
+  if (overlaps(b, x, h->len * 8)) return FMP_ERR_ALIAS;
+  size_t need = 0;
+  fmp_status st = fmp_solve_workspace(h, o, &need);
+  if (st) return st;
+  if (ws_bytes < need || ((uintptr_t)ws) % kAlign) return FMP_ERR_WORKSPACE;
+  if (o->precond && !h->precond_ok) return FMP_ERR_UNSUPPORTED;
+  fmp_solve_info local{};
+  Ctx c{h, (hipStream_t)stream, o, &local};
+  const auto t0 = std::chrono::steady_clock::now();
+  st = (o->solver == 0) ? bicgstab(c, b, x, (double*)ws) : fgmres(c, b, x, (double*)ws);
+  if (hipStreamSynchronize(c.s) != hipSuccess && st >= 0) st = FMP_ERR_HIP;
+  local.t_total_ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (info) *info = local;
+  return st;
+}

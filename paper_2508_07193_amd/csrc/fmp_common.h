@@ -1,0 +1,131 @@
+// Internal declarations shared by the FlashMP HIP sources (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "flashmp.h"
+
+namespace fmp {
+
+// Largest box side with a compiled transform class, and the row stride of
+// every transform table (tables are stored kTS x kTS, zero padded).
+constexpr int kMaxSide = 48;
+constexpr int kTS = 48;
+
+// Transform size classes: a box of largest side n runs the kernels compiled
+// for the smallest class >= n (zero-padded rows/columns cost flops only).
+constexpr int kClasses[] = {8, 16, 24, 26, 32, 34, 40, 48};
+constexpr int kNumClasses = sizeof(kClasses) / sizeof(kClasses[0]);
+
+struct DomainDev {
+  int nx, ny, nz;
+  int eps_b;            // permittivity cube side (0 = eps 1)
+  long long offset;     // element offset of this domain's block in a vector
+  double c;
+  int eps_off;          // offset into the eps table array
+  int eps_nbx, eps_nby, eps_nbz;
+};
+
+// One RAS box.  Table offsets index the per-precision table arrays:
+// dct[a] / dst[a] are kTS x kTS matrices for the box side along axis a,
+// sig[a] the singular values sigma_m = 2 sin(m pi / (2 n)).
+struct BoxDev {
+  int dom;
+  int bx0, by0, bz0;    // box origin (cells, in the domain)
+  int nx, ny, nz;       // box sides
+  int ox0, oy0, oz0;    // owned block origin
+  int sx, sy, sz;       // owned block sides
+  int sub;              // global subdomain index (coarse vector entry)
+  int dct[3], dst[3], sig[3];
+  int pad;
+  long long w_off;      // staging offset (elements) of component 0
+  long long vol;        // nx*ny*nz
+  double alpha;         // c / mean eps over the owned block
+};
+
+// Stencil tile: 64 x 4 columns marching over zc planes of one domain.
+struct StencilTile {
+  int dom, x0, y0, z0;
+};
+
+constexpr int kStencilTX = 64, kStencilTY = 4, kStencilZC = 16;
+
+// Fixed reduction geometry: stage 1 uses kRedBlocks blocks of 256 threads.
+constexpr int kRedBlocks = 1024;
+constexpr int kMaxDots = 34;    // CGS: up to restart+1 basis vectors + ||w||^2
+
+// ---- launchers (defined in the .hip files) ---------------------------------
+hipError_t launch_curlcurl(const double* x, double* y, const DomainDev* doms,
+                           const StencilTile* tiles, int ntiles, const double* eps,
+                           hipStream_t s);
+
+// Transform passes for one size class over a range of work items.
+// prec: 0 fp64, 1 fp32 (vector ALU); tables typed accordingly.
+hipError_t launch_pass_a(int prec, int cls, const double* r, void* W, const BoxDev* boxes,
+                         const DomainDev* doms, const int4* work, int nwork, const void* tab,
+                         hipStream_t s);
+hipError_t launch_pass_b(int prec, int cls, void* W, const BoxDev* boxes, const int4* work,
+                         int nwork, const void* tab, hipStream_t s);
+hipError_t launch_pass_c(int prec, int cls, const void* W, double* z, const BoxDev* boxes,
+                         const DomainDev* doms, const int4* work, int nwork, const void* tab,
+                         const double* coarse, int nsub, hipStream_t s);
+int pass_a_zslab(int cls);   // planes per pass-A/C work item for a class
+
+// BF16 MFMA transform passes (staging in FP32).
+hipError_t launch_mfma_pass_a(int cls, const double* r, float* W, const BoxDev* boxes,
+                              const DomainDev* doms, const int4* work, int nwork,
+                              const __hip_bfloat16* tab, hipStream_t s);
+hipError_t launch_mfma_pass_b(int cls, float* W, const BoxDev* boxes, const int4* work,
+                              int nwork, const __hip_bfloat16* tab, const float* sig,
+                              hipStream_t s);
+hipError_t launch_mfma_pass_c(int cls, const float* W, double* z, const BoxDev* boxes,
+                              const DomainDev* doms, const int4* work, int nwork,
+                              const __hip_bfloat16* tab, const double* coarse, int nsub,
+                              hipStream_t s);
+int mfma_zslab(int cls);
+
+// ---- Krylov vector kernels -------------------------------------------------
+// Dots <a_i, b_i> for i < n: partials[blk * n + i]; then reduce to out[i].
+struct DotPtrs {
+  const double* a[8];
+  const double* b[8];
+};
+hipError_t launch_dots(const DotPtrs& p, int n, long long len, double* partials, hipStream_t s);
+// Multi-dot h_i = <V_i, w> (i < nv) and h_nv = <w, w>; V_i = V + i * ldv.
+hipError_t launch_mdot(const double* V, long long ldv, int nv, const double* w, long long len,
+                       double* partials, hipStream_t s);
+// Final fixed-order reduction of `n` partial columns into out[0..n); post-op
+// codes run on thread 0 after the sums (see fmp_krylov.hip).
+hipError_t launch_reduce(const double* partials, int n, double* out, int post, double* S,
+                         hipStream_t s);
+// w -= sum_i h_i V_i, partial ||w||^2 into partials (n = 1).
+hipError_t launch_mupdate(const double* V, long long ldv, int nv, const double* h, double* w,
+                          long long len, double* partials, hipStream_t s);
+// x += sum_i y_i Z_i.
+hipError_t launch_xupdate(const double* Z, long long ldz, int nz, const double* y, double* x,
+                          long long len, hipStream_t s);
+hipError_t launch_axpby(double a, const double* x, double b, const double* y, double* out,
+                        long long len, hipStream_t s);   // out = a x + b y
+hipError_t launch_scale_copy(const double* x, double a, double* out, long long len,
+                             hipStream_t s);              // out = a x
+hipError_t launch_sub_norm(const double* b, const double* y, double* r, long long len,
+                           double* partials, hipStream_t s);  // r = b - y, partial ||r||^2
+// BiCGSTAB fused steps (scalars live in device array S; see fmp_krylov.hip).
+hipError_t launch_bicg_p(const double* r, double* p, const double* v, const double* S,
+                         long long len, hipStream_t s);
+hipError_t launch_bicg_s(const double* r, const double* v, double* sv, const double* S,
+                         long long len, hipStream_t s);
+hipError_t launch_bicg_xr(double* x, const double* phat, const double* shat, const double* sv,
+                          const double* t, double* r, const double* rhat, const double* S,
+                          long long len, double* partials, hipStream_t s);
+
+// ---- learned coarse correction ---------------------------------------------
+hipError_t launch_coarse_restrict(const double* r, const BoxDev* boxes, int nbox,
+                                  const DomainDev* doms, double* rc, hipStream_t s);
+
+}  // namespace fmp

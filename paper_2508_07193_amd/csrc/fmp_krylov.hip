@@ -1,0 +1,324 @@
+// FP64 vector kernels of the Krylov drivers (Sec. IV-A; Table III work per iteration).
+//
+// Reductions are two-stage with a fixed geometry: kRedBlocks blocks of 256
+// threads each sum a fixed, strided subset of the elements, reduce inside the
+// block in a fixed tree, and write one partial per block; a single block then
+// sums the partials in a fixed order.  No atomics, so results are bitwise
+// reproducible run to run.
+//
+// Scalars of BiCGSTAB live in a small device array S so that consecutive
+// kernels consume them without a round trip to the host:
+//   S[0] rho = <rhat, r>   S[1] rho_prev   S[2] alpha   S[3] omega
+//   S[4] <rhat, v>         S[5] <t, s>     S[6] <t, t>  S[7] ||r||^2
+//   S[8] beta
+#include "fmp_common.h"
+
+namespace fmp {
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+// Reduce acc[0..n) over the block; thread 0 of each wave stores to lds, then
+// threads i < n combine the 4 wave sums in order and write partials[i][blk].
+template <int N>
+__device__ __forceinline__ void block_store(const double (&acc)[N], int n, double* partials) {
+  __shared__ double red[4][N];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    if (i < n) {
+      const double s = wave_sum(acc[i]);
+      if (lane == 0) red[wave][i] = s;
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < n) {
+    const int i = threadIdx.x;
+    partials[(long long)i * kRedBlocks + blockIdx.x] =
+        ((red[0][i] + red[1][i]) + red[2][i]) + red[3][i];
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_dots(DotPtrs P, int n, long long len,
+                                                   double* __restrict__ partials) {
+  double acc[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) acc[i] = 0.0;
+  const long long stride = (long long)kRedBlocks * kThreads;
+  for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < len; e += stride) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      if (i < n) acc[i] = __builtin_fma(P.a[i][e], P.b[i][e], acc[i]);
+  }
+  block_store<8>(acc, n, partials);
+}
+
+template <int NV>
+__global__ __launch_bounds__(kThreads) void k_mdot(const double* __restrict__ V, long long ldv,
+                                                   int nv, const double* __restrict__ w,
+                                                   long long len, double* __restrict__ partials) {
+  double acc[NV + 1];
+#pragma unroll
+  for (int i = 0; i <= NV; ++i) acc[i] = 0.0;
+  const long long stride = (long long)kRedBlocks * kThreads;
+  for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < len; e += stride) {
+    const double we = w[e];
+#pragma unroll
+    for (int i = 0; i < NV; ++i)
+      if (i < nv) acc[i] = __builtin_fma(V[i * ldv + e], we, acc[i]);
+    acc[NV] = __builtin_fma(we, we, acc[NV]);
+  }
+  // move <w,w> to slot nv so that partial columns are 0..nv
+  double out[NV + 1];
+#pragma unroll
+  for (int i = 0; i <= NV; ++i) out[i] = (i < nv) ? acc[i] : (i == nv ? acc[NV] : 0.0);
+  block_store<NV + 1>(out, nv + 1, partials);
+}
+
+template <int NV>
+__global__ __launch_bounds__(kThreads) void k_mupdate(const double* __restrict__ V, long long ldv,
+                                                      int nv, const double* __restrict__ h,
+                                                      double* __restrict__ w, long long len,
+                                                      double* __restrict__ partials) {
+  double hh[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) hh[i] = (i < nv) ? h[i] : 0.0;
+  double acc[1] = {0.0};
+  const long long stride = (long long)kRedBlocks * kThreads;
+  for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < len; e += stride) {
+    double we = w[e];
+#pragma unroll
+    for (int i = 0; i < NV; ++i)
+      if (i < nv) we = __builtin_fma(-hh[i], V[i * ldv + e], we);
+    w[e] = we;
+    acc[0] = __builtin_fma(we, we, acc[0]);
+  }
+  block_store<1>(acc, 1, partials);
+}
+
+template <int NV>
+__global__ __launch_bounds__(kThreads) void k_xupdate(const double* __restrict__ Z, long long ldz,
+                                                      int nz, const double* __restrict__ y,
+                                                      double* __restrict__ x, long long len) {
+  double yy[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) yy[i] = (i < nz) ? y[i] : 0.0;
+  const long long stride = (long long)gridDim.x * kThreads;
+  for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < len; e += stride) {
+    double xe = x[e];
+#pragma unroll
+    for (int i = 0; i < NV; ++i)
+      if (i < nz) xe = __builtin_fma(yy[i], Z[i * ldz + e], xe);
+    x[e] = xe;
+  }
+}
+
+// post-op codes of the final reduction
+enum { POST_NONE = 0, POST_ALPHA = 1, POST_OMEGA = 2, POST_RHO = 3 };
+
+__global__ __launch_bounds__(kThreads) void k_reduce(const double* __restrict__ partials, int n,
+                                                     double* __restrict__ out, int post,
+                                                     double* __restrict__ S) {
+  __shared__ double red[4];
+  __shared__ double res[kMaxDots];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  for (int i = 0; i < n; ++i) {
+    const double* p = partials + (long long)i * kRedBlocks;
+    double v = 0.0;
+#pragma unroll
+    for (int k = 0; k < kRedBlocks / kThreads; ++k) v += p[k * kThreads + t];
+    v = wave_sum(v);
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    if (t == 0) res[i] = ((red[0] + red[1]) + red[2]) + red[3];
+    __syncthreads();
+  }
+  if (t == 0) {
+    for (int i = 0; i < n; ++i) out[i] = res[i];
+    if (post == POST_ALPHA) {
+      S[2] = S[0] / res[0];
+    } else if (post == POST_OMEGA) {
+      S[3] = res[1] > 0.0 ? res[0] / res[1] : 0.0;
+    } else if (post == POST_RHO) {
+      const double rho_new = res[1];
+      S[8] = (rho_new / S[0]) * (S[2] / S[3]);
+      S[1] = S[0];
+      S[0] = rho_new;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_axpby(double a, const double* __restrict__ x,
+                                                    double b, const double* __restrict__ y,
+                                                    double* __restrict__ out, long long len) {
+  const long long stride = (long long)gridDim.x * kThreads;
+  for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < len; e += stride)
+    out[e] = a * x[e] + b * y[e];
+}
+
+__global__ __launch_bounds__(kThreads) void k_scale_copy(const double* __restrict__ x, double a,
+                                                         double* __restrict__ out, long long len) {
+  const long long stride = (long long)gridDim.x * kThreads;
+  for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < len; e += stride)
+    out[e] = a * x[e];
+}
+
+__global__ __launch_bounds__(kThreads) void k_sub_norm(const double* __restrict__ b,
+                                                       const double* __restrict__ y,
+                                                       double* __restrict__ r, long long len,
+                                                       double* __restrict__ partials) {
+  double acc[1] = {0.0};
+  const long long stride = (long long)kRedBlocks * kThreads;
+  for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < len; e += stride) {
+    const double v = b[e] - y[e];
+    r[e] = v;
+    acc[0] = __builtin_fma(v, v, acc[0]);
+  }
+  block_store<1>(acc, 1, partials);
+}
+
+__global__ __launch_bounds__(kThreads) void k_bicg_p(const double* __restrict__ r,
+                                                     double* __restrict__ p,
+                                                     const double* __restrict__ v,
+                                                     const double* __restrict__ S, long long len) {
+  const double beta = S[8], omega = S[3];
+  const long long stride = (long long)gridDim.x * kThreads;
+  for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < len; e += stride)
+    p[e] = r[e] + beta * (p[e] - omega * v[e]);
+}
+
+__global__ __launch_bounds__(kThreads) void k_bicg_s(const double* __restrict__ r,
+                                                     const double* __restrict__ v,
+                                                     double* __restrict__ sv,
+                                                     const double* __restrict__ S, long long len) {
+  const double alpha = S[2];
+  const long long stride = (long long)gridDim.x * kThreads;
+  for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < len; e += stride)
+    sv[e] = r[e] - alpha * v[e];
+}
+
+__global__ __launch_bounds__(kThreads) void k_bicg_xr(double* __restrict__ x,
+                                                      const double* __restrict__ phat,
+                                                      const double* __restrict__ shat,
+                                                      const double* __restrict__ sv,
+                                                      const double* __restrict__ t,
+                                                      double* __restrict__ r,
+                                                      const double* __restrict__ rhat,
+                                                      const double* __restrict__ S, long long len,
+                                                      double* __restrict__ partials) {
+  const double alpha = S[2], omega = S[3];
+  double acc[2] = {0.0, 0.0};
+  const long long stride = (long long)kRedBlocks * kThreads;
+  for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < len; e += stride) {
+    x[e] = x[e] + alpha * phat[e] + omega * shat[e];
+    const double re = sv[e] - omega * t[e];
+    r[e] = re;
+    acc[0] = __builtin_fma(re, re, acc[0]);
+    acc[1] = __builtin_fma(rhat[e], re, acc[1]);
+  }
+  block_store<2>(acc, 2, partials);
+}
+
+int grid_for(long long len) {
+  long long g = (len + kThreads - 1) / kThreads;
+  if (g > 4096) g = 4096;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+}  // namespace
+
+hipError_t launch_dots(const DotPtrs& p, int n, long long len, double* partials, hipStream_t s) {
+  if (n < 1 || n > 8) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_dots, dim3(kRedBlocks), dim3(kThreads), 0, s, p, n, len, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_mdot(const double* V, long long ldv, int nv, const double* w, long long len,
+                       double* partials, hipStream_t s) {
+  if (nv < 1 || nv + 1 > kMaxDots) return hipErrorInvalidValue;
+#define L(NV) hipLaunchKernelGGL((k_mdot<NV>), dim3(kRedBlocks), dim3(kThreads), 0, s, V, ldv, nv, w, len, partials)
+  if (nv <= 4) L(4);
+  else if (nv <= 8) L(8);
+  else if (nv <= 16) L(16);
+  else L(33);
+#undef L
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(const double* partials, int n, double* out, int post, double* S,
+                         hipStream_t s) {
+  if (n < 1 || n > kMaxDots) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kThreads), 0, s, partials, n, out, post, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_mupdate(const double* V, long long ldv, int nv, const double* h, double* w,
+                          long long len, double* partials, hipStream_t s) {
+  if (nv < 1 || nv > 33) return hipErrorInvalidValue;
+#define L(NV) hipLaunchKernelGGL((k_mupdate<NV>), dim3(kRedBlocks), dim3(kThreads), 0, s, V, ldv, nv, h, w, len, partials)
+  if (nv <= 4) L(4);
+  else if (nv <= 8) L(8);
+  else if (nv <= 16) L(16);
+  else L(33);
+#undef L
+  return hipGetLastError();
+}
+
+hipError_t launch_xupdate(const double* Z, long long ldz, int nz, const double* y, double* x,
+                          long long len, hipStream_t s) {
+  if (nz < 1 || nz > 33) return hipErrorInvalidValue;
+#define L(NV) hipLaunchKernelGGL((k_xupdate<NV>), dim3(grid_for(len)), dim3(kThreads), 0, s, Z, ldz, nz, y, x, len)
+  if (nz <= 4) L(4);
+  else if (nz <= 8) L(8);
+  else if (nz <= 16) L(16);
+  else L(33);
+#undef L
+  return hipGetLastError();
+}
+
+hipError_t launch_axpby(double a, const double* x, double b, const double* y, double* out,
+                        long long len, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpby, dim3(grid_for(len)), dim3(kThreads), 0, s, a, x, b, y, out, len);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_copy(const double* x, double a, double* out, long long len,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_copy, dim3(grid_for(len)), dim3(kThreads), 0, s, x, a, out, len);
+  return hipGetLastError();
+}
+
+hipError_t launch_sub_norm(const double* b, const double* y, double* r, long long len,
+                           double* partials, hipStream_t s) {
+  hipLaunchKernelGGL(k_sub_norm, dim3(kRedBlocks), dim3(kThreads), 0, s, b, y, r, len, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_bicg_p(const double* r, double* p, const double* v, const double* S,
+                         long long len, hipStream_t s) {
+  hipLaunchKernelGGL(k_bicg_p, dim3(grid_for(len)), dim3(kThreads), 0, s, r, p, v, S, len);
+  return hipGetLastError();
+}
+
+hipError_t launch_bicg_s(const double* r, const double* v, double* sv, const double* S,
+                         long long len, hipStream_t s) {
+  hipLaunchKernelGGL(k_bicg_s, dim3(grid_for(len)), dim3(kThreads), 0, s, r, v, sv, S, len);
+  return hipGetLastError();
+}
+
+hipError_t launch_bicg_xr(double* x, const double* phat, const double* shat, const double* sv,
+                          const double* t, double* r, const double* rhat, const double* S,
+                          long long len, double* partials, hipStream_t s) {
+  hipLaunchKernelGGL(k_bicg_xr, dim3(kRedBlocks), dim3(kThreads), 0, s, x, phat, shat, sv, t, r,
+                     rhat, S, len, partials);
+  return hipGetLastError();
+}
+
+}  // namespace fmp

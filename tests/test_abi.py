@@ -1,0 +1,79 @@
+"""Host-side checks of the C ABI (no GPU needed): symbols, size queries, argument errors."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2508_07193_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_symbols():
+    src = open(os.path.join(ROOT, "include", "flashmp.h")).read()
+    return sorted(set(re.findall(r"\b(fmp_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("library not built")
+    return _lib.load()
+
+
+def test_exports_every_declared_symbol(L):
+    declared = _header_symbols()
+    assert set(declared) == set(_lib.EXPORTS)
+    for name in declared:
+        assert hasattr(L, name), name
+
+
+def _desc(n=64, sub=32, c=2.0):
+    d = _lib.DomainDesc()
+    d.nx = d.ny = d.nz = n
+    d.c = c
+    d.eps_block = None
+    d.eps_block_size = 0
+    d.sub_x = d.sub_y = d.sub_z = sub
+    return d
+
+
+def _size(L, descs, overlap=1, prec=0):
+    arr = (_lib.DomainDesc * len(descs))(*descs)
+    pd = _lib.PrecondDesc(overlap, prec, 0, 0)
+    nb = C.c_size_t(0)
+    h = C.c_void_p()
+    st = L.fmp_setup_subdomains(arr, len(descs), C.byref(pd), None, C.byref(nb), None, C.byref(h))
+    return st, nb.value
+
+
+def test_workspace_query_runs_on_host(L):
+    st, nb = _size(L, [_desc()])
+    assert st == 0
+    # staging for 8 boxes of side 33 (each touches three walls) in FP64 plus tables
+    assert nb >= 3 * 8 * 33**3 * 8
+    st32, nb32 = _size(L, [_desc()], prec=1)
+    assert st32 == 0 and nb32 < nb
+
+
+@pytest.mark.parametrize("kw,want", [
+    (dict(overlap=0), -1),            # overlap must be >= 1
+    (dict(n=30, sub=32), -1),         # sub must divide the side
+    (dict(n=1, sub=0), -1),           # side < 2
+])
+def test_invalid_descriptors(L, kw, want):
+    overlap = kw.pop("overlap", 1)
+    st, _ = _size(L, [_desc(**kw)], overlap=overlap)
+    assert st == want
+
+
+def test_oversized_boxes_still_get_a_workspace_size(L):
+    # box side 66 exceeds the largest transform class: setup sizes the stencil-only handle
+    st, nb = _size(L, [_desc(n=128, sub=64)])
+    assert st == 0 and 0 < nb < 3 * 8 * 66**3 * 8
+
+
+def test_status_strings(L):
+    assert L.fmp_status_string(0) == b"ok"
+    assert L.fmp_status_string(-2) == b"input and output overlap"

@@ -1,0 +1,267 @@
+"""Parity of the HIP path (through the C ABI) with the CPU FP64 oracle.
+
+Tolerances (FP64): the stencil sums at most 13 products of an integer weight
+and a value, scaled once by c/eps; its rounding error is below
+16 u (1 + 12 c/eps_min) max|x| with u = 2^-53, so 1e-13 max|x| bounds it for
+the c <= 8 used here.  The transform solve applies six orthogonal contractions
+of length <= 34 and a pointwise 3x3 solve; each contraction adds at most
+34 u relative error in the max norm, so 1e-12 relative (max norm) is a safe
+bound with margin for the box solve's conditioning (eigenvalues of B in
+[1, 1 + 12 alpha]).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import krylov, ras, transforms, yee
+from paper_2508_07193_amd import api, inputs
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64).ravel()).to(DEV)
+
+
+def host(t, shape):
+    torch.cuda.synchronize()
+    return t.cpu().numpy().reshape(shape)
+
+
+def handle_for(P, **kw):
+    return api.Handle([dict(nx=P["nx"], ny=P["ny"], nz=P["nz"], c=P["c"], eps=P["eps"],
+                            eps_block=P.get("eps_block", 0), sub=P["sub"])], device=DEV, **kw)
+
+
+def eps_cell_of(P):
+    if P["eps"] is None:
+        return None
+    return yee.expand_eps(P["eps"], P["eps_block"], P["nx"], P["ny"], P["nz"])
+
+
+def relmax(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def problem(n, sub, c, eps_block, seed):
+    return inputs.make_problem(dict(n=n, sub=sub, c=c, eps_block=eps_block, seed=seed))
+
+
+# ------------------------------------------------------------------ stencil
+def test_stencil_integer_inputs_bitwise():
+    nx, ny, nz = 70, 10, 19           # ragged against the 64 x 4 x 16 tiles
+    rng = np.random.default_rng(0)
+    v = rng.integers(-8, 9, size=(3, nz, ny, nx)).astype(np.float64)
+    # garbage on the wall slots must be ignored
+    mask = inputs.unknown_slots(nx, ny, nz)
+    ref = yee.apply_A_padded(np.where(mask, v, 0.0), 2.0)
+    h = api.Handle([dict(nx=nx, ny=ny, nz=nz, c=2.0)], device=DEV)
+    y = h.new_vector()
+    h.curlcurl_apply(dev(v), y)
+    out = host(y, ref.shape)
+    assert np.array_equal(out, ref)
+
+
+@pytest.mark.parametrize("shape,blk,c", [((40, 36, 34), 4, 2.0), ((17, 23, 9), 3, 8.0)])
+def test_stencil_random_eps(shape, blk, c):
+    nx, ny, nz = shape
+    rng = np.random.default_rng(1)
+    eps = inputs.eps_table(rng, -(-nx // blk) * blk, -(-ny // blk) * blk, -(-nz // blk) * blk, blk)
+    v = inputs.normal_rhs(rng, nx, ny, nz)
+    ref = yee.apply_A_padded(v, c, yee.expand_eps(eps, blk, nx, ny, nz))
+    h = api.Handle([dict(nx=nx, ny=ny, nz=nz, c=c, eps=eps, eps_block=blk)], device=DEV)
+    y = h.new_vector()
+    h.curlcurl_apply(dev(v), y)
+    out = host(y, ref.shape)
+    assert np.abs(out - ref).max() <= 1e-13 * np.abs(v).max()
+
+
+def test_stencil_two_domains():
+    rng = np.random.default_rng(2)
+    d1 = dict(nx=12, ny=16, nz=8, c=0.5)
+    d2 = dict(nx=24, ny=24, nz=24, c=3.0)
+    v1 = inputs.normal_rhs(rng, 12, 16, 8)
+    v2 = inputs.normal_rhs(rng, 24, 24, 24)
+    h = api.Handle([d1, d2], device=DEV)
+    assert h.offsets == [0, v1.size, v1.size + v2.size]
+    y = h.new_vector()
+    h.curlcurl_apply(torch.cat([dev(v1), dev(v2)]), y)
+    out = y.cpu().numpy()
+    r1 = yee.apply_A_padded(v1, 0.5)
+    r2 = yee.apply_A_padded(v2, 3.0)
+    assert relmax(out[:v1.size].reshape(r1.shape), r1) < 1e-14
+    assert relmax(out[v1.size:].reshape(r2.shape), r2) < 1e-14
+
+
+# ------------------------------------------------------------------ preconditioner
+@pytest.mark.parametrize("n,sub,c,blk,overlap", [
+    (32, 16, 2.0, 8, 1),               # 8 boxes of 17^3
+    (48, 16, 8.0, 8, 1),               # 27 boxes of sides {17, 18}
+    (24, 8, 2.0, 4, 2),                # overlap 2, boxes {10, 12}
+    (16, 0, 0.5, 0, 1),                # one box = the whole domain (C1 shape)
+])
+def test_precond_fp64_matches_oracle(n, sub, c, blk, overlap):
+    P = problem(n, sub, c, blk, seed=n + sub)
+    h = handle_for(P, overlap=overlap)
+    r = P["rhs"].copy()
+    garbage = np.where(inputs.unknown_slots(n, n, n), r, 123.0)   # walls ignored on input
+    z = h.new_vector()
+    h.apply_precond(dev(garbage), z)
+    ref = ras.ras_apply(r, c, P["sub"], overlap, eps_cell_of(P))
+    out = host(z, ref.shape)
+    assert relmax(out, ref) < 1e-12
+    assert np.all(out[~inputs.unknown_slots(n, n, n)] == 0.0)
+
+
+def test_precond_anisotropic_domain():
+    nx, ny, nz, sub, c = 48, 32, 24, (16, 16, 8), 1.5
+    rng = np.random.default_rng(5)
+    eps = inputs.eps_table(rng, nx, ny, nz, 8)
+    r = inputs.normal_rhs(rng, nx, ny, nz)
+    h = api.Handle([dict(nx=nx, ny=ny, nz=nz, c=c, eps=eps, eps_block=8, sub=sub)], device=DEV)
+    z = h.new_vector()
+    h.apply_precond(dev(r), z)
+    ref = ras.ras_apply(r, c, sub, 1, yee.expand_eps(eps, 8, nx, ny, nz))
+    assert relmax(host(z, ref.shape), ref) < 1e-12
+
+
+def test_precond_fp32_error_bound():
+    P = problem(32, 16, 2.0, 8, seed=7)
+    h = handle_for(P, precision="fp32")
+    z = h.new_vector()
+    h.apply_precond(dev(P["rhs"]), z)
+    ref = ras.ras_apply(P["rhs"], 2.0, P["sub"], 1, eps_cell_of(P))
+    # six FP32 contractions of length <= 18: error ~ 1e-6 relative in the max norm
+    assert relmax(host(z, ref.shape), ref) < 2e-5
+
+
+def test_precond_batching_and_determinism():
+    P = problem(48, 16, 2.0, 8, seed=9)
+    r = dev(P["rhs"])
+    outs = []
+    for bb in (0, 5, 1):
+        h = handle_for(P, batch_boxes=bb)
+        z = h.new_vector()
+        h.apply_precond(r, z)
+        outs.append(z.clone())
+        z2 = h.new_vector()
+        h.apply_precond(r, z2)
+        assert torch.equal(z, z2)
+    assert torch.equal(outs[0], outs[1]) and torch.equal(outs[0], outs[2])
+
+
+def test_alias_is_rejected():
+    P = problem(16, 8, 2.0, 0, seed=1)
+    h = handle_for(P)
+    r = dev(P["rhs"])
+    with pytest.raises(api.FlashMPError, match="ALIAS"):
+        h.apply_precond(r, r)
+    with pytest.raises(api.FlashMPError, match="ALIAS"):
+        h.curlcurl_apply(r, r)
+
+
+# ------------------------------------------------------------------ solvers
+def _oracle_ops(P):
+    eps_cell = eps_cell_of(P)
+    nx, ny, nz = P["nx"], P["ny"], P["nz"]
+    A = yee.assemble_A(nx, ny, nz, P["c"], eps_cell)
+    Af = lambda v: yee.to_padded(A @ yee.from_padded(v), nx, ny, nz)
+    Mf = lambda v: ras.ras_apply(v, P["c"], P["sub"], 1, eps_cell)
+    return A, Af, Mf
+
+
+@pytest.mark.parametrize("solver", ["bicgstab", "fgmres"])
+def test_solve_matches_oracle_iterations(solver):
+    P = problem(32, 16, 2.0, 8, seed=2)
+    A, Af, Mf = _oracle_ops(P)
+    b = P["rhs"]
+    if solver == "bicgstab":
+        xo, io = krylov.bicgstab(Af, b, M=Mf, tol=1e-8)
+    else:
+        xo, io = krylov.fgmres(Af, b, M=Mf, tol=1e-8, restart=30)
+    h = handle_for(P)
+    x = h.new_vector()
+    info = h.solve(dev(b), x, solver=solver, rtol=1e-8, max_iter=300, check_every=1)
+    assert info["status"] == "FMP_OK"
+    assert info["rel_residual_true"] <= 1e-8
+    assert abs(info["iterations"] - io["iterations"]) <= 1, (info, io["iterations"])
+    xs = host(x, b.shape)
+    # the GPU's true residual, recomputed on the CPU
+    res = np.linalg.norm(yee.from_padded(b) - A @ yee.from_padded(xs)) / np.linalg.norm(b)
+    assert res <= 1.5e-8
+    assert relmax(xs, xo) < 1e-6
+
+
+def test_solve_unpreconditioned_and_restart():
+    P = problem(16, 8, 2.0, 4, seed=3)
+    A, Af, _ = _oracle_ops(P)
+    b = P["rhs"]
+    xo, io = krylov.fgmres(Af, b, tol=1e-8, restart=10)
+    h = handle_for(P)
+    x = h.new_vector()
+    info = h.solve(dev(b), x, solver="fgmres", restart=10, precond=False, rtol=1e-8,
+                   max_iter=1000)
+    assert info["status"] == "FMP_OK"
+    assert abs(info["iterations"] - io["iterations"]) <= 2, (info, io["iterations"])
+
+
+def test_c1_one_exact_solve():
+    """16^3 single box, c = 0.5: BiCGSTAB with the exact solve converges in one iteration."""
+    P = inputs.make_problem("c1")
+    h = handle_for(P)
+    b = dev(P["rhs"])
+    z = h.new_vector()
+    h.apply_precond(b, z)
+    ref = yee.to_padded(transforms.box_solve_transform(yee.from_padded(P["rhs"]), 16, 16, 16, 0.5),
+                        16, 16, 16)
+    assert relmax(host(z, ref.shape), ref) < 1e-12
+    x = h.new_vector()
+    info = h.solve(b, x, solver="bicgstab", rtol=1e-10, max_iter=10)
+    assert info["status"] == "FMP_OK" and info["iterations"] == 1
+    assert info["rel_residual_true"] < 1e-10
+
+
+def test_failure_paths():
+    P = problem(16, 8, 2.0, 0, seed=4)
+    h = handle_for(P)
+    b = dev(P["rhs"])
+    x = h.new_vector()
+    info = h.solve(b, x, solver="fgmres", rtol=1e-12, max_iter=1)
+    assert info["status"] == "FMP_NOT_CONVERGED" and info["iterations"] == 1
+    bn = b.clone()
+    bn[100] = float("nan")
+    x = h.new_vector()
+    with pytest.raises(api.FlashMPError, match="BREAKDOWN"):
+        h.solve(bn, x, solver="bicgstab", rtol=1e-8, max_iter=5)
+
+
+# ------------------------------------------------------------------ full-size samples
+@pytest.mark.slow
+def test_full_256_sampled_stencil_and_precond():
+    """256^3, 8^3 subdomains of 32^3, eps U[1,10] on 8^3 cubes, c = 2 (the launch bench.py times)."""
+    P = inputs.make_problem("c3")
+    n = 256
+    eps_cell = eps_cell_of(P)
+    h = handle_for(P)
+    r = dev(P["rhs"])
+    y = h.new_vector()
+    z = h.new_vector()
+    h.curlcurl_apply(r, y)
+    h.apply_precond(r, z)
+    yo = host(y, P["rhs"].shape)
+    zo = host(z, P["rhs"].shape)
+    rng = np.random.default_rng(0)
+    pts = [(int(q), int(k), int(j), int(i)) for q, k, j, i in
+           zip(rng.integers(0, 3, 150), rng.integers(0, n, 150), rng.integers(0, n, 150),
+               rng.integers(0, n, 150))]
+    pts += [(0, 1, 1, 0), (1, 255, 0, 255), (2, 0, 255, 255), (0, 255, 255, 255)]
+    ref = yee.apply_A_at(P["rhs"], P["c"], eps_cell, pts)
+    got = np.array([yo[p] for p in pts])
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(P["rhs"]).max()
+    # corner, edge, face and interior subdomains (index = (sz*8 + sy)*8 + sx)
+    which = [0, 7, 63, 511, 8 * 64 + 3 * 8 + 4, 3 * 64 + 4 * 8 + 5]
+    blocks = ras.ras_apply_subset(P["rhs"], P["c"], P["sub"], 1, eps_cell, which)
+    for idx, (own, blk) in blocks.items():
+        (x0, x1), (y0, y1), (z0, z1) = own
+        assert relmax(zo[:, z0:z1, y0:y1, x0:x1], blk) < 1e-12, idx
