@@ -1,0 +1,64 @@
+"""Pins of the learned-correction oracle: gradients by finite differences,
+restriction/prolongation identities, Adam's first step, bf16 rounding."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import coarse
+from paper_2508_07193_amd import inputs
+
+
+def _params(n_in, hidden, seed=0):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(coarse.n_params(n_in, hidden)) * 0.5
+
+
+def test_backward_matches_central_differences():
+    n_in, hidden, batch = 6, 5, 4
+    rng = np.random.default_rng(1)
+    p = _params(n_in, hidden)
+    X = rng.standard_normal((batch, n_in))
+    Y = rng.standard_normal((batch, n_in))
+    _, g = coarse.loss_grad(p, X, Y, n_in, hidden)
+    h = 1e-6
+    fd = np.zeros_like(p)
+    for i in range(p.size):
+        e = np.zeros_like(p)
+        e[i] = h
+        fd[i] = (coarse.loss_grad(p + e, X, Y, n_in, hidden)[0] -
+                 coarse.loss_grad(p - e, X, Y, n_in, hidden)[0]) / (2 * h)
+    assert np.abs(fd - g).max() <= 1e-7 * max(1.0, np.abs(g).max())
+
+
+def test_forward_small_case_by_hand():
+    """One input, hidden 1: O = W3 relu(W2 relu(W1 x + b1) + b2) + b3."""
+    n_in, hidden = 1, 1
+    p = np.array([2.0, -1.0, 3.0, 0.5, -2.0, 0.25])   # W1 b1 W2 b2 W3 b3
+    O, _ = coarse.forward(p, np.array([[1.5]]), n_in, hidden)
+    h1 = max(2.0 * 1.5 - 1.0, 0.0)
+    h2 = max(3.0 * h1 + 0.5, 0.0)
+    assert O[0, 0] == -2.0 * h2 + 0.25
+
+
+def test_restrict_prolong_identities():
+    n, sub = 16, (8, 8, 8)
+    rng = np.random.default_rng(2)
+    y = rng.standard_normal(3 * 8)
+    z = coarse.prolong(y, (3, n, n, n), sub)
+    assert np.allclose(coarse.restrict(z, sub), y, rtol=0, atol=1e-15)
+    assert np.all(z[~inputs.unknown_slots(n, n, n)] == 0)
+    # a field equal to 1 on every unknown averages to 1 everywhere
+    ones = inputs.unknown_slots(n, n, n).astype(float)
+    assert np.allclose(coarse.restrict(ones, sub), 1.0)
+
+
+def test_adam_first_step_is_signed_lr():
+    g = np.array([3.0, -0.5, 1e-3])
+    p, m, v = coarse.adam(np.zeros(3), g, np.zeros(3), np.zeros(3), 1, 1e-2)
+    np.testing.assert_allclose(p, -1e-2 * np.sign(g), rtol=1e-4)
+
+
+def test_bf16_rounding_matches_torch():
+    x = np.random.default_rng(3).standard_normal(10000).astype(np.float32) * 7
+    ref = torch.from_numpy(x).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(coarse.bf16_round(x), ref)
