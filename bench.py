@@ -69,14 +69,68 @@ def cpu_baseline(P, iters, sample_boxes=12):
                 seconds_measured=round((t_pre * sample_boxes / nsub) + t_spmv / 1 + t_vec, 2))
 
 
+def learned_leg(args, dev, log):
+    """256^3, c = 8: FGMRES with and without the trained coarse correction.
+
+    Pairs: args.pairs_rhs right-hand sides (seeds 1005+) x args.pairs_per_rhs
+    FGMRES iterates; held-out right-hand sides: seeds 2005..2009.
+    """
+    import torch
+    from paper_2508_07193_amd import api, inputs, learned
+    P = inputs.make_problem("c5")
+    n = P["nx"]
+    dom = dict(nx=n, ny=n, nz=n, c=P["c"], eps=P["eps"], eps_block=P["eps_block"], sub=P["sub"])
+    h = api.Handle([dom], overlap=1, precision="fp64", use_learned=True, device=dev)
+    t0 = time.perf_counter()
+    X, Y = learned.generate_pairs(h, (n, n, n), args.pairs_rhs, args.pairs_per_rhs, 1005, log=log)
+    t_pairs = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    params, hist = learned.train(X, Y, hidden=256, epochs=args.epochs, batch=100, lr=1e-3,
+                                 device=dev, log=log)
+    t_train = time.perf_counter() - t0
+    res = {"plain": [], "learned": []}
+    x = h.new_vector()
+    for mode in ("plain", "learned"):
+        api.fmp_set_coarse_model(h, 256, params if mode == "learned" else None)
+        for sd in range(2005, 2010):
+            b = torch.from_numpy(inputs.extra_rhs(n, n, n, sd).ravel()).to(dev)
+            x.zero_()
+            h.solve(b, x, solver="fgmres", rtol=1e-8, max_iter=500)      # warm
+            x.zero_()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            info = h.solve(b, x, solver="fgmres", rtol=1e-8, max_iter=500)
+            torch.cuda.synchronize()
+            info["wall_ms"] = (time.perf_counter() - t1) * 1e3
+            res[mode].append(info)
+    it_p = float(np.mean([r["iterations"] for r in res["plain"]]))
+    it_l = float(np.mean([r["iterations"] for r in res["learned"]]))
+    ms_p = float(np.mean([r["wall_ms"] for r in res["plain"]]))
+    ms_l = float(np.mean([r["wall_ms"] for r in res["learned"]]))
+    log(f"[learned] plain {it_p} it {ms_p:.1f} ms, learned {it_l} it {ms_l:.1f} ms")
+    return dict(workload="256^3, c=8, eps_r U[1,10] 8^3 cubes, FGMRES(30) FP64 to 1e-8; "
+                         "held-out RHS seeds 2005-2009",
+                pairs=int(X.shape[0]), pair_generation_s=round(t_pairs, 1),
+                train_s=round(t_train, 1), final_train_mse=hist[-1], first_epoch_mse=hist[0],
+                plain_iterations=it_p, learned_iterations=it_l,
+                plain_time_to_solution_ms=round(ms_p, 2), learned_time_to_solution_ms=round(ms_l, 2),
+                learned_fallbacks=[r["used_fallback"] for r in res["learned"]],
+                learned_rel_residual_true=max(r["rel_residual_true"] for r in res["learned"]),
+                speedup_vs_plain=round(ms_p / ms_l, 3))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c3")
-    ap.add_argument("--variants", default="fp32")
+    ap.add_argument("--variants", default="fp32,bf16")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--learned", type=int, default=1, help="run the C5 learned-correction leg")
+    ap.add_argument("--pairs-rhs", type=int, default=200)
+    ap.add_argument("--pairs-per-rhs", type=int, default=10)
+    ap.add_argument("--epochs", type=int, default=150)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the solver has no multi-GPU path "
@@ -180,6 +234,11 @@ def main():
         except Exception as e:  # report, do not hide
             out["variants"][prec] = dict(error=str(e))
 
+    if args.learned:
+        try:
+            out["variants"]["learned_c5"] = learned_leg(args, dev, log)
+        except Exception as e:  # report, do not hide
+            out["variants"]["learned_c5"] = dict(error=str(e))
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(P, info64["iterations"])
     print(json.dumps(out), flush=True)

@@ -85,18 +85,27 @@ typedef struct {
  * use_learned: 1 reserves room for a coarse-correction network
  *   (fmp_set_coarse_model); it is applied only once weights are set.
  * batch_boxes: boxes per pipeline batch (0 = automatic); smaller batches keep
- *   the transform staging resident in the last-level cache. */
+ *   the transform staging resident in the last-level cache.
+ * use_graph: 1 = the launch sequence of an apply is captured once per
+ *   (r, z) pair into a hipGraph (on a private stream, default priority) and
+ *   replayed on the caller's stream; at most 64 pairs are cached, further
+ *   pairs run uncaptured.  Results are identical to uncaptured applies. */
 typedef struct {
   int32_t overlap;
   int32_t precision;
   int32_t use_learned;
   int32_t batch_boxes;
+  int32_t use_graph;
 } fmp_precond_desc;
 
 /* Krylov options.  solver: 0 = BiCGSTAB, 1 = flexible GMRES(restart).
  * rtol: stop when ||b - A x||_2 / ||b - A x0||_2 <= rtol (Sec. IV-A).
- * precond: 0 = none (identity), 1 = FlashMP RAS (+ learned part if set).
- * check_every: host convergence check period for BiCGSTAB (>= 1). */
+ * precond: 0 = none (identity), 1 = FlashMP RAS (+ learned part if set; the
+ *   learned part is used by FGMRES only, judged per step by the FP64 residual).
+ * check_every: host convergence check period for BiCGSTAB (>= 1).
+ * capture_count, capture: FGMRES only; if capture_count > 0, the iterates
+ *   x_1 .. x_capture_count are written to the device buffer capture
+ *   (capture_count vectors of fmp_vector_layout length, caller-owned). */
 typedef struct {
   int32_t solver;
   int32_t restart;
@@ -104,6 +113,8 @@ typedef struct {
   double rtol;
   int32_t precond;
   int32_t check_every;
+  int32_t capture_count;
+  double* capture;
 } fmp_solve_opts;
 
 typedef struct {

@@ -25,12 +25,13 @@ class DomainDesc(C.Structure):
 
 class PrecondDesc(C.Structure):
     _fields_ = [("overlap", C.c_int32), ("precision", C.c_int32), ("use_learned", C.c_int32),
-                ("batch_boxes", C.c_int32)]
+                ("batch_boxes", C.c_int32), ("use_graph", C.c_int32)]
 
 
 class SolveOpts(C.Structure):
     _fields_ = [("solver", C.c_int32), ("restart", C.c_int32), ("max_iter", C.c_int32),
-                ("rtol", C.c_double), ("precond", C.c_int32), ("check_every", C.c_int32)]
+                ("rtol", C.c_double), ("precond", C.c_int32), ("check_every", C.c_int32),
+                ("capture_count", C.c_int32), ("capture", C.c_void_p)]
 
 
 class SolveInfo(C.Structure):

@@ -64,7 +64,7 @@ class Handle:
     """A set of domains with their RAS plans (fmp_setup_subdomains) and workspace."""
 
     def __init__(self, domains, overlap=1, precision="fp64", use_learned=False, batch_boxes=0,
-                 device="cuda", stream=None):
+                 use_graph=False, device="cuda", stream=None):
         L = _lib.load()
         keep = []
         arr = (_lib.DomainDesc * len(domains))()
@@ -73,7 +73,7 @@ class Handle:
             arr[i] = d
             keep.append(k)
         pd = _lib.PrecondDesc(int(overlap), _lib.PRECISION[precision], int(bool(use_learned)),
-                              int(batch_boxes))
+                              int(batch_boxes), int(bool(use_graph)))
         nbytes = C.c_size_t(0)
         h = C.c_void_p()
         s = _stream(stream)
@@ -130,9 +130,14 @@ def fmp_apply_precond(h, r, z, stream=None):
            "fmp_apply_precond", h.h)
 
 
-def solve_opts(solver="fgmres", restart=30, max_iter=500, rtol=1e-8, precond=True, check_every=1):
-    return _lib.SolveOpts({"bicgstab": 0, "fgmres": 1}[solver], int(restart), int(max_iter),
-                          float(rtol), int(bool(precond)), int(check_every))
+def solve_opts(solver="fgmres", restart=30, max_iter=500, rtol=1e-8, precond=True, check_every=1,
+               capture=None):
+    o = _lib.SolveOpts({"bicgstab": 0, "fgmres": 1}[solver], int(restart), int(max_iter),
+                       float(rtol), int(bool(precond)), int(check_every), 0, None)
+    if capture is not None:   # (count, length) float64 CUDA tensor receiving x_1 .. x_count
+        o.capture_count = int(capture.shape[0])
+        o.capture = C.c_void_p(capture.data_ptr())
+    return o
 
 
 def fmp_solve(h, b, x, stream=None, raise_on_breakdown=True, **kw):
@@ -156,3 +161,41 @@ def fmp_solve(h, b, x, stream=None, raise_on_breakdown=True, **kw):
 
 def release_solver_workspace(h):
     h._solve_ws = None
+
+
+# ---------------------------------------------------------------- learned coarse correction
+def fmp_coarse_size(h):
+    n = C.c_int32(0)
+    _check(_lib.load().fmp_coarse_size(h.h, C.byref(n)), "fmp_coarse_size", h.h)
+    return int(n.value)
+
+
+def fmp_set_coarse_model(h, hidden, params):
+    """Upload FP32 parameters (flat, see include/flashmp.h); None disables the correction."""
+    L = _lib.load()
+    if params is None:
+        _check(L.fmp_set_coarse_model(h.h, 0, None, 0), "fmp_set_coarse_model", h.h)
+        return
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    _check(L.fmp_set_coarse_model(h.h, int(hidden), p.ctypes.data_as(C.POINTER(C.c_float)),
+                                  p.nbytes), "fmp_set_coarse_model", h.h)
+
+
+def fmp_coarse_restrict(h, r, rc, stream=None):
+    _check(_lib.load().fmp_coarse_restrict(h.h, _ptr(r), _ptr(rc), _stream(stream)),
+           "fmp_coarse_restrict", h.h)
+
+
+def fmp_mlp_scratch_bytes(in_dim, hidden, batch):
+    return int(_lib.load().fmp_mlp_scratch_bytes(in_dim, hidden, batch))
+
+
+def fmp_mlp_loss_grad(in_dim, hidden, batch, params, X, Y, grads, loss, scratch, stream=None):
+    _check(_lib.load().fmp_mlp_loss_grad(in_dim, hidden, batch, _ptr(params), _ptr(X), _ptr(Y),
+                                         _ptr(grads), _ptr(loss), _ptr(scratch), scratch.numel(),
+                                         _stream(stream)), "fmp_mlp_loss_grad")
+
+
+def fmp_mlp_adam(params, grads, m, v, t, lr, stream=None):
+    _check(_lib.load().fmp_mlp_adam(params.numel(), _ptr(params), _ptr(grads), _ptr(m), _ptr(v),
+                                    int(t), float(lr), _stream(stream)), "fmp_mlp_adam")

@@ -21,58 +21,21 @@
 #include <memory>
 
 #include "fmp_common.h"
+#include "fmp_ctx.h"
 
 using namespace fmp;
-
-struct Launch {
-  int cls;
-  int a0, na;   // pass A / C work items
-  int b0, nb;   // pass B work items
-};
-
-struct fmp_ctx {
-  std::vector<DomainDev> doms;
-  std::vector<BoxDev> boxes;
-  std::vector<long long> offsets;
-  std::vector<Launch> launches;
-  int prec = 0;
-  int overlap = 1;
-  bool precond_ok = true;      // every box side has a compiled transform class
-  int nsub = 0;
-  long long len = 0;
-  int ntiles = 0;
-  // device regions inside the workspace
-  DomainDev* d_doms = nullptr;
-  BoxDev* d_boxes = nullptr;
-  StencilTile* d_tiles = nullptr;
-  double* d_eps = nullptr;
-  void* d_tab = nullptr;
-  float* d_sig32 = nullptr;
-  int4* d_work_a = nullptr;
-  int4* d_work_b = nullptr;
-  void* d_W = nullptr;
-  double* d_part = nullptr;
-  double* d_S = nullptr;
-  // learned coarse correction
-  bool use_learned = false;
-  bool learned_set = false;
-  int hidden = 0;
-  double* d_rc = nullptr;      // R0 r (3*nsub), then the scaled correction
-  void* d_mlp = nullptr;       // weights + activations
-  size_t mlp_bytes = 0;
-  double* h_S = nullptr;       // pinned host mirror of scalars
-  std::string err;
-};
 
 namespace {
 
 constexpr size_t kAlign = 256;
+constexpr int kTB = 64;         // row stride of the bf16 tables
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 constexpr int kScal = 256;      // doubles in the scalar area
 constexpr int kScalH = 16;      // h column of FGMRES
 constexpr int kScalW = 64;      // ||w||^2
 constexpr int kScalY = 128;     // FGMRES update coefficients
+constexpr int kScalJ = 200;     // learned-correction judge: ||v - w||^2, ||v - w + A d||^2
 
 struct Parts {
   int own0, own1, box0, box1;
@@ -145,8 +108,42 @@ uint16_t to_bf16(double x) {
 }  // namespace
 
 // ============================================================== precond / spmv
+static fmp_status precond_launches(fmp_ctx* h, const double* r, double* z, hipStream_t s,
+                                   const double* coarse);
+
+// Replay (or capture, on first use of this (r, z) pair) the launch sequence of
+// one apply as a hipGraph.  Capture runs on the handle's private stream; the
+// instantiated graph is launched on the caller's stream.
 static fmp_status precond_apply(fmp_ctx* h, const double* r, double* z, hipStream_t s,
                                 const double* coarse) {
+  if (!h->use_graph) return precond_launches(h, r, z, s, coarse);
+  for (const auto& g : h->graphs)
+    if (g.r == r && g.z == z && g.coarse == (coarse != nullptr)) {
+      HIPCHK(h, hipGraphLaunch(g.exec, s));
+      return FMP_OK;
+    }
+  if (h->graphs.size() >= 64) return precond_launches(h, r, z, s, coarse);
+  if (!h->cap_stream) HIPCHK(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+  hipGraph_t graph = nullptr;
+  HIPCHK(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+  const fmp_status st = precond_launches(h, r, z, h->cap_stream, coarse);
+  const hipError_t e = hipStreamEndCapture(h->cap_stream, &graph);
+  if (st != FMP_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (e != hipSuccess) return hip_fail(h, e, "hipStreamEndCapture");
+  hipGraphExec_t exec = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ei != hipSuccess) return hip_fail(h, ei, "hipGraphInstantiate");
+  h->graphs.push_back({r, z, coarse != nullptr, exec});
+  HIPCHK(h, hipGraphLaunch(exec, s));
+  return FMP_OK;
+}
+
+static fmp_status precond_launches(fmp_ctx* h, const double* r, double* z, hipStream_t s,
+                                   const double* coarse) {
   const int prec = h->prec;
   for (const Launch& L : h->launches) {
     if (prec == FMP_BF16) {
@@ -177,6 +174,8 @@ static fmp_status spmv(fmp_ctx* h, const double* x, double* y, hipStream_t s) {
 // Learned part: defined in fmp_coarse.hip (returns the device correction
 // vector to add in pass C, or nullptr when the model is not set).
 fmp_status fmp_coarse_forward(fmp_ctx* h, const double* r, hipStream_t s, const double** out);
+hipError_t fmp_coarse_judge(fmp_ctx* h, const double* v, const double* w, double* partials,
+                            hipStream_t s);
 size_t fmp_coarse_workspace(int nsub, int hidden_max);
 void fmp_coarse_bind(fmp_ctx* h, void* base);
 
@@ -209,6 +208,7 @@ fmp_status fmp_setup_subdomains(const fmp_domain_desc* domains, int32_t n_domain
   h->prec = pd->precision;
   h->overlap = pd->overlap;
   h->use_learned = pd->use_learned != 0;
+  h->use_graph = pd->use_graph != 0;
 
   // ---- domains, boxes, eps tables
   std::vector<double> eps_all;
@@ -242,6 +242,9 @@ fmp_status fmp_setup_subdomains(const fmp_domain_desc* domains, int32_t n_domain
         eps_all.push_back(e);
       }
     }
+    dd.sx = sub[0]; dd.sy = sub[1]; dd.sz = sub[2];
+    dd.px = D.nx / sub[0]; dd.py = D.ny / sub[1]; dd.pz = D.nz / sub[2];
+    dd.sub0 = h->nsub;
     h->doms.push_back(dd);
     h->offsets.push_back(off);
     off += 3LL * D.nx * D.ny * D.nz;
@@ -287,7 +290,7 @@ fmp_status fmp_setup_subdomains(const fmp_domain_desc* domains, int32_t n_domain
   int nsides = 0;
   for (int n = 2; n <= kMaxSide; ++n)
     if (sides_used[n]) side_slot[n] = nsides++;
-  const long long per_side = 2LL * kTS * kTS + kTS;   // dct, dst, sig
+  const long long per_side = 3LL * kTS * kTS + kTS;   // dct, dct^T, dst, sig
   std::vector<double> tab64((size_t)(per_side * nsides), 0.0);
   {
     std::vector<double> c, s, g;
@@ -296,8 +299,10 @@ fmp_status fmp_setup_subdomains(const fmp_domain_desc* domains, int32_t n_domain
       basis_tables(n, c, s, g);
       double* base = tab64.data() + side_slot[n] * per_side;
       std::copy(c.begin(), c.end(), base);
-      std::copy(s.begin(), s.end(), base + kTS * kTS);
-      std::copy(g.begin(), g.end(), base + 2 * kTS * kTS);
+      for (int i = 0; i < kTS; ++i)
+        for (int j = 0; j < kTS; ++j) base[kTS * kTS + i * kTS + j] = c[j * kTS + i];
+      std::copy(s.begin(), s.end(), base + 2 * kTS * kTS);
+      std::copy(g.begin(), g.end(), base + 3 * kTS * kTS);
     }
   }
   if (!h->precond_ok) h->boxes.clear();   // stencil and unpreconditioned solves only
@@ -306,8 +311,29 @@ fmp_status fmp_setup_subdomains(const fmp_domain_desc* domains, int32_t n_domain
     for (int a = 0; a < 3; ++a) {
       const int base = (int)(side_slot[sides[a]] * per_side);
       B.dct[a] = base;
-      B.dst[a] = base + kTS * kTS;
-      B.sig[a] = base + 2 * kTS * kTS;
+      B.dctT[a] = base + kTS * kTS;
+      B.dst[a] = base + 2 * kTS * kTS;
+      B.sig[a] = base + 3 * kTS * kTS;
+      const int mbase = side_slot[sides[a]] * 3 * kTB * kTB;
+      B.mdct[a] = mbase;
+      B.mdctT[a] = mbase + kTB * kTB;
+      B.mdst[a] = mbase + 2 * kTB * kTB;
+    }
+  }
+  // bf16 copies for the MFMA passes: Bt[n][k] with row stride kTB (zero padded)
+  std::vector<uint16_t> tab16;
+  if (h->prec == FMP_BF16) {
+    tab16.assign((size_t)nsides * 3 * kTB * kTB, 0);
+    for (int n = 2; n <= kMaxSide; ++n) {
+      if (side_slot[n] < 0) continue;
+      const double* base = tab64.data() + side_slot[n] * per_side;
+      uint16_t* mb = tab16.data() + (size_t)side_slot[n] * 3 * kTB * kTB;
+      for (int i = 0; i < kTS; ++i)
+        for (int j = 0; j < kTS; ++j) {
+          mb[i * kTB + j] = to_bf16(base[i * kTS + j]);                              // DCT-II
+          mb[kTB * kTB + i * kTB + j] = to_bf16(base[j * kTS + i]);                  // DCT-II^T
+          mb[2 * kTB * kTB + i * kTB + j] = to_bf16(base[2 * kTS * kTS + i * kTS + j]);  // DST-I
+        }
     }
   }
 
@@ -364,8 +390,9 @@ fmp_status fmp_setup_subdomains(const fmp_domain_desc* domains, int32_t n_domain
   const size_t o_boxes = cur; cur = align_up(cur + h->boxes.size() * sizeof(BoxDev));
   const size_t o_tiles = cur; cur = align_up(cur + tiles.size() * sizeof(StencilTile));
   const size_t o_eps = cur; cur = align_up(cur + std::max<size_t>(1, eps_all.size()) * 8);
-  const size_t o_tab = cur; cur = align_up(cur + tab64.size() * tsz);
-  const size_t o_sig32 = cur; cur = align_up(cur + tab64.size() * 4);
+  const size_t tab_bytes = (h->prec == FMP_BF16) ? tab16.size() * 2 : tab64.size() * tsz;
+  const size_t o_tab = cur; cur = align_up(cur + std::max<size_t>(tab_bytes, 1));
+  const size_t o_sig32 = cur; cur = align_up(cur + std::max<size_t>(tab64.size() * 4, 1));
   const size_t o_wa = cur; cur = align_up(cur + work_a.size() * sizeof(int4));
   const size_t o_wb = cur; cur = align_up(cur + work_b.size() * sizeof(int4));
   const size_t o_part = cur; cur = align_up(cur + (size_t)kMaxDots * kRedBlocks * 8);
@@ -397,14 +424,14 @@ fmp_status fmp_setup_subdomains(const fmp_domain_desc* domains, int32_t n_domain
   if (h->use_learned) fmp_coarse_bind(h.get(), base + o_learn);
 
   // typed tables
-  std::vector<char> tabbytes(tab64.size() * tsz);
+  std::vector<char> tabbytes(tab_bytes);
   std::vector<float> sig32(tab64.size());
   for (size_t i = 0; i < tab64.size(); ++i) {
     sig32[i] = (float)tab64[i];
     if (h->prec == FMP_FP64) memcpy(&tabbytes[i * 8], &tab64[i], 8);
     else if (h->prec == FMP_FP32) { float f = (float)tab64[i]; memcpy(&tabbytes[i * 4], &f, 4); }
-    else { uint16_t b = to_bf16(tab64[i]); memcpy(&tabbytes[i * 2], &b, 2); }
   }
+  if (h->prec == FMP_BF16 && tab_bytes) memcpy(tabbytes.data(), tab16.data(), tab_bytes);
   hipStream_t s = (hipStream_t)stream;
   fmp_ctx* hp = h.get();
   HIPCHK(hp, hipMemcpyAsync(h->d_doms, h->doms.data(), h->doms.size() * sizeof(DomainDev),
@@ -415,8 +442,10 @@ fmp_status fmp_setup_subdomains(const fmp_domain_desc* domains, int32_t n_domain
                             hipMemcpyHostToDevice, s));
   if (!eps_all.empty())
     HIPCHK(hp, hipMemcpyAsync(h->d_eps, eps_all.data(), eps_all.size() * 8, hipMemcpyHostToDevice, s));
-  HIPCHK(hp, hipMemcpyAsync(h->d_tab, tabbytes.data(), tabbytes.size(), hipMemcpyHostToDevice, s));
-  HIPCHK(hp, hipMemcpyAsync(h->d_sig32, sig32.data(), sig32.size() * 4, hipMemcpyHostToDevice, s));
+  if (!tabbytes.empty())
+    HIPCHK(hp, hipMemcpyAsync(h->d_tab, tabbytes.data(), tabbytes.size(), hipMemcpyHostToDevice, s));
+  if (!sig32.empty())
+    HIPCHK(hp, hipMemcpyAsync(h->d_sig32, sig32.data(), sig32.size() * 4, hipMemcpyHostToDevice, s));
   HIPCHK(hp, hipMemcpyAsync(h->d_work_a, work_a.data(), work_a.size() * sizeof(int4),
                             hipMemcpyHostToDevice, s));
   HIPCHK(hp, hipMemcpyAsync(h->d_work_b, work_b.data(), work_b.size() * sizeof(int4),
@@ -436,6 +465,8 @@ fmp_status fmp_vector_layout(fmp_handle h, int64_t* offsets) {
 fmp_status fmp_destroy(fmp_handle h) {
   if (!h) return FMP_ERR_INVALID_ARG;
   if (h->h_S) (void)hipHostFree(h->h_S);
+  for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.exec);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   delete h;
   return FMP_OK;
 }
@@ -485,14 +516,16 @@ struct Ctx {
   fmp_solve_info* info;
 };
 
-fmp_status M(Ctx& c, const double* r, double* z) {
+// z = M^{-1} r; the learned coarse correction is added only where the caller
+// can judge it (FGMRES), since BiCGSTAB assumes a fixed linear preconditioner.
+fmp_status M(Ctx& c, const double* r, double* z, bool learned = false) {
   c.info->n_precond++;
   if (c.o->precond == 0) {
     HIPCHK(c.h, launch_scale_copy(r, 1.0, z, c.h->len, c.s));
     return FMP_OK;
   }
   const double* coarse = nullptr;
-  if (c.h->learned_set) {
+  if (learned && c.h->learned_set) {
     fmp_status st = fmp_coarse_forward(c.h, r, c.s, &coarse);
     if (st != FMP_OK) return st;
   }
@@ -609,8 +642,23 @@ fmp_status fgmres(Ctx& c, const double* b, double* x, double* ws) {
       double* vj = V + (size_t)j * vb;
       double* zj = Z + (size_t)j * vb;
       double* w = V + (size_t)(j + 1) * vb;
-      if ((st = M(c, vj, zj))) return st;
+      const bool learned = c.o->precond != 0 && h->learned_set;
+      if ((st = M(c, vj, zj, learned))) return st;
       if ((st = A(c, zj, w))) return st;
+      if (learned) {
+        // the FP64 residual judges the correction: keep it only if
+        // ||v - A z|| does not exceed the plain preconditioner's ||v - A z_RAS||
+        HIPCHK(h, fmp_coarse_judge(h, vj, w, h->d_part, c.s));
+        HIPCHK(h, launch_reduce(h->d_part, 2, h->d_S + kScalJ, 0, h->d_S, c.s));
+        HIPCHK(h, hipMemcpyAsync(hs + kScalJ, h->d_S + kScalJ, 16, hipMemcpyDeviceToHost, c.s));
+        HIPCHK(h, hipStreamSynchronize(c.s));
+        if (!(hs[kScalJ] <= hs[kScalJ + 1])) {
+          c.info->used_fallback++;
+          c.info->n_precond++;
+          if ((st = precond_apply(h, vj, zj, c.s, nullptr))) return st;
+          if ((st = A(c, zj, w))) return st;
+        }
+      }
       // classical Gram-Schmidt: h = V^T w (and ||w||^2), w -= V h, ||w||^2
       HIPCHK(h, launch_mdot(V, (long long)vb, j + 1, w, n, h->d_part, c.s));
       HIPCHK(h, launch_reduce(h->d_part, j + 2, h->d_S + kScalH, 0, h->d_S, c.s));
@@ -649,6 +697,19 @@ fmp_status fgmres(Ctx& c, const double* b, double* x, double* ws) {
       g[j] = cs[j] * g[j];
       ++it;
       ncols = j + 1;
+      if (c.o->capture && it <= c.o->capture_count) {   // x_it = x + Z y for the current LS solution
+        for (int i = ncols - 1; i >= 0; --i) {
+          double acc = g[i];
+          for (int k = i + 1; k < ncols; ++k) acc -= H[i * m + k] * y[k];
+          y[i] = acc / H[i * m + i];
+        }
+        for (int i = 0; i < ncols; ++i) hs[kScalY + i] = y[i];
+        double* slot = c.o->capture + (size_t)(it - 1) * n;
+        HIPCHK(h, hipMemcpyAsync(h->d_S + kScalY, hs + kScalY, ncols * 8, hipMemcpyHostToDevice, c.s));
+        HIPCHK(h, hipMemcpyAsync(slot, x, n * 8, hipMemcpyDeviceToDevice, c.s));
+        HIPCHK(h, launch_xupdate(Z, (long long)vb, ncols, h->d_S + kScalY, slot, n, c.s));
+        HIPCHK(h, hipStreamSynchronize(c.s));
+      }
       if (hn == 0.0 || fabs(g[j + 1]) <= tol * r0 || it >= c.o->max_iter) break;
       HIPCHK(h, launch_scale_copy(w, 1.0 / hn, w, n, c.s));
     }
@@ -677,6 +738,8 @@ extern "C" fmp_status fmp_solve(fmp_handle h, const double* b, double* x, const 
                                 void* ws, size_t ws_bytes, fmp_solve_info* info, void* stream) {
   if (!h || !b || !x || !o || !ws) return FMP_ERR_INVALID_ARG;
   if (o->max_iter < 1 || !(o->rtol > 0.0)) return FMP_ERR_INVALID_ARG;
+  if (o->capture_count < 0 || (o->capture_count > 0 && (!o->capture || o->solver != 1)))
+    return FMP_ERR_INVALID_ARG;
   if (overlaps(b, x, h->len * 8)) return FMP_ERR_ALIAS;
   size_t need = 0;
   fmp_status st = fmp_solve_workspace(h, o, &need);

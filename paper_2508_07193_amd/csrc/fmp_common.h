@@ -29,11 +29,15 @@ struct DomainDev {
   double c;
   int eps_off;          // offset into the eps table array
   int eps_nbx, eps_nby, eps_nbz;
+  int sx, sy, sz;       // owned subdomain sides
+  int px, py, pz;       // subdomains per axis
+  int sub0;             // global index of the domain's first subdomain
 };
 
 // One RAS box.  Table offsets index the per-precision table arrays:
-// dct[a] / dst[a] are kTS x kTS matrices for the box side along axis a,
-// sig[a] the singular values sigma_m = 2 sin(m pi / (2 n)).
+// dct[a] / dst[a] are kTS x kTS matrices for the box side along axis a
+// (dctT[a] the transposed DCT-II; DST-I is symmetric), sig[a] the singular
+// values sigma_m = 2 sin(m pi / (2 n)).
 struct BoxDev {
   int dom;
   int bx0, by0, bz0;    // box origin (cells, in the domain)
@@ -41,8 +45,8 @@ struct BoxDev {
   int ox0, oy0, oz0;    // owned block origin
   int sx, sy, sz;       // owned block sides
   int sub;              // global subdomain index (coarse vector entry)
-  int dct[3], dst[3], sig[3];
-  int pad;
+  int dct[3], dctT[3], dst[3], sig[3];
+  int mdct[3], mdctT[3], mdst[3];   // bf16 tables (row stride 64) of the MFMA passes
   long long w_off;      // staging offset (elements) of component 0
   long long vol;        // nx*ny*nz
   double alpha;         // c / mean eps over the owned block

@@ -1,0 +1,71 @@
+// Handle of the FlashMP library (internal; shared by the host-side sources).
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "fmp_common.h"
+
+using fmp::BoxDev;
+using fmp::DomainDev;
+using fmp::StencilTile;
+
+struct Launch {
+  int cls;
+  int a0, na;   // pass A / C work items
+  int b0, nb;   // pass B work items
+};
+
+struct fmp_ctx {
+  std::vector<DomainDev> doms;
+  std::vector<BoxDev> boxes;
+  std::vector<long long> offsets;
+  std::vector<Launch> launches;
+  int prec = 0;
+  int overlap = 1;
+  bool precond_ok = true;      // every box side has a compiled transform class
+  int nsub = 0;
+  long long len = 0;
+  int ntiles = 0;
+  // device regions inside the workspace
+  DomainDev* d_doms = nullptr;
+  BoxDev* d_boxes = nullptr;
+  StencilTile* d_tiles = nullptr;
+  double* d_eps = nullptr;
+  void* d_tab = nullptr;
+  float* d_sig32 = nullptr;
+  int4* d_work_a = nullptr;
+  int4* d_work_b = nullptr;
+  void* d_W = nullptr;
+  double* d_part = nullptr;
+  double* d_S = nullptr;
+  // learned coarse correction (layout in fmp_coarse.hip)
+  bool use_learned = false;
+  bool learned_set = false;
+  int hidden = 0;
+  double* d_rc = nullptr;      // R0 r, [3][nsub]
+  double* d_yc = nullptr;      // correction to inject, [3][nsub]
+  double* d_cS = nullptr;      // scalars of the coarse step (norm of R0 r)
+  float* d_u = nullptr;        // MLP input (R0 r / ||R0 r||)
+  float* d_h1 = nullptr;
+  float* d_h2 = nullptr;
+  __hip_bfloat16* d_W1 = nullptr;
+  __hip_bfloat16* d_W2 = nullptr;
+  __hip_bfloat16* d_W3 = nullptr;
+  float* d_b1 = nullptr;
+  float* d_b2 = nullptr;
+  float* d_b3 = nullptr;
+  double* h_S = nullptr;       // pinned host mirror of scalars
+  // captured preconditioner applies, keyed by (r, z, learned part active)
+  struct Graph {
+    const double* r;
+    double* z;
+    bool coarse;
+    hipGraphExec_t exec;
+  };
+  bool use_graph = false;
+  hipStream_t cap_stream = nullptr;
+  std::vector<Graph> graphs;
+  std::string err;
+};
+

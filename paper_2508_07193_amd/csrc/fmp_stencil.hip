@@ -10,107 +10,115 @@
 // and the E_y, E_z rows follow by the cyclic relabelling x -> y -> z -> x.
 // Values outside the domain or on a wall slot are zero.
 //
-// Mapping: a 64 x 4 tile of (i, j) columns per workgroup marches over 16
-// z-planes.  Each lane keeps the values of its own column at k-1, k, k+1 in
-// registers; in-plane neighbours come through L1/L2 (their owners load the
-// same lines in the same step).  HBM traffic is then close to the algorithmic
-// 8 bytes in + 8 bytes out per unknown.
+// Mapping: a workgroup owns a 64 x 4 tile of (i, j) columns and marches over
+// kStencilZC z-planes.  Three rolling LDS planes (k-1, k, k+1) of all three
+// components, with a one-cell halo in x and y, are filled by coalesced loads
+// that zero wall slots and out-of-domain cells once, so the stencil itself
+// reads LDS without bounds checks.  Cell permittivities of planes k-1 and k
+// are staged the same way.  HBM sees each value once (halos come from L2),
+// i.e. the algorithmic 8 bytes in + 8 bytes out per unknown.
+//
+// Tiles are enumerated x fastest, then y, then z; the block index is
+// remapped so that each XCD (blocks are dealt to the 8 XCDs round-robin)
+// works on a contiguous run of tiles and finds their halos in its own L2.
 #include "fmp_common.h"
 
 namespace fmp {
 namespace {
 
-struct Dims {
-  int nx, ny, nz;
-  long long cs;  // component stride nz*ny*nx
-};
+constexpr int TX = kStencilTX, TY = kStencilTY;
+constexpr int HX = TX + 2, HY = TY + 2;   // tile with halo
 
-template <int Q>
-__device__ __forceinline__ double ld(const double* __restrict__ b, const Dims& d, int k, int j,
-                                     int i) {
-  if (i < 0 || j < 0 || k < 0 || i >= d.nx || j >= d.ny || k >= d.nz) return 0.0;
-  // the two node axes of component Q hold the wall in slot 0
-  if (Q == 0 && (j == 0 || k == 0)) return 0.0;
-  if (Q == 1 && (i == 0 || k == 0)) return 0.0;
-  if (Q == 2 && (i == 0 || j == 0)) return 0.0;
-  return b[Q * d.cs + ((long long)k * d.ny + j) * d.nx + i];
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+  const int q = nb / 8, r = nb % 8;
+  const int x = b % 8, idx = b / 8;
+  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + idx;
 }
 
-__device__ __forceinline__ double cell_eps(const double* __restrict__ e, const DomainDev& D, int i,
-                                           int j, int k) {
-  const int b = D.eps_b;
-  return e[D.eps_off + ((k / b) * D.eps_nby + (j / b)) * D.eps_nbx + (i / b)];
-}
-
-__global__ __launch_bounds__(256) void k_curlcurl(const double* __restrict__ x,
-                                                  double* __restrict__ y,
-                                                  const DomainDev* __restrict__ doms,
-                                                  const StencilTile* __restrict__ tiles,
-                                                  const double* __restrict__ eps) {
-  const StencilTile T = tiles[blockIdx.x];
+__global__ __launch_bounds__(TX * TY) void k_curlcurl(const double* __restrict__ x,
+                                                      double* __restrict__ y,
+                                                      const DomainDev* __restrict__ doms,
+                                                      const StencilTile* __restrict__ tiles,
+                                                      int ntiles, const double* __restrict__ eps) {
+  __shared__ double P[3][3][HY][HX];          // [slot][component][j][i]
+  __shared__ double E[2][TY + 1][TX + 1];     // cell eps, [slot][j][i] for cells j0-1.., i0-1..
+  const StencilTile T = tiles[xcd_remap(blockIdx.x, ntiles)];
   const DomainDev D = doms[T.dom];
-  const int i = T.x0 + (int)(threadIdx.x % kStencilTX);
-  const int j = T.y0 + (int)(threadIdx.x / kStencilTX);
-  if (i >= D.nx || j >= D.ny) return;
-  const Dims d{D.nx, D.ny, D.nz, (long long)D.nz * D.ny * D.nx};
-  const double* xb = x + D.offset;
-  double* yb = y + D.offset;
-  const int k0 = T.z0, k1 = min(T.z0 + kStencilZC, D.nz);
+  const int nx = D.nx, ny = D.ny, nz = D.nz;
+  const long long cs = (long long)nz * ny * nx;
+  const double* __restrict__ xb = x + D.offset;
+  double* __restrict__ yb = y + D.offset;
+  const int t = threadIdx.x;
+  const int tx = t % TX, ty = t / TX;
+  const int i = T.x0 + tx, j = T.y0 + ty;
+  const int k0 = T.z0, k1 = min(T.z0 + kStencilZC, nz);
+  const bool use_eps = D.eps_b > 0;
 
-  // rolling own-column values
-  double exm = ld<0>(xb, d, k0 - 1, j, i), ex0 = ld<0>(xb, d, k0, j, i);
-  double eym = ld<1>(xb, d, k0 - 1, j, i), ey0 = ld<1>(xb, d, k0, j, i);
-  double ezm = ld<2>(xb, d, k0 - 1, j, i);
-  for (int k = k0; k < k1; ++k) {
-    const double exp1 = ld<0>(xb, d, k + 1, j, i);
-    const double eyp1 = ld<1>(xb, d, k + 1, j, i);
-    const double ez0 = ld<2>(xb, d, k, j, i);
-
-    // E_x row at (i+1/2, j, k)
-    const double kx = 4.0 * ex0 - ld<0>(xb, d, k, j + 1, i) - ld<0>(xb, d, k, j - 1, i) - exp1 -
-                      exm + (ld<1>(xb, d, k, j, i + 1) - ey0 - ld<1>(xb, d, k, j - 1, i + 1) +
-                             ld<1>(xb, d, k, j - 1, i)) +
-                      (ld<2>(xb, d, k, j, i + 1) - ez0 - ld<2>(xb, d, k - 1, j, i + 1) + ezm);
-    // E_y row at (i, j+1/2, k)
-    const double ky = 4.0 * ey0 - eyp1 - eym - ld<1>(xb, d, k, j, i + 1) -
-                      ld<1>(xb, d, k, j, i - 1) +
-                      (ld<2>(xb, d, k, j + 1, i) - ez0 - ld<2>(xb, d, k - 1, j + 1, i) + ezm) +
-                      (ld<0>(xb, d, k, j + 1, i) - ex0 - ld<0>(xb, d, k, j + 1, i - 1) +
-                       ld<0>(xb, d, k, j, i - 1));
-    // E_z row at (i, j, k+1/2)
-    const double kz = 4.0 * ez0 - ld<2>(xb, d, k, j, i + 1) - ld<2>(xb, d, k, j, i - 1) -
-                      ld<2>(xb, d, k, j + 1, i) - ld<2>(xb, d, k, j - 1, i) +
-                      (exp1 - ex0 - ld<0>(xb, d, k + 1, j, i - 1) + ld<0>(xb, d, k, j, i - 1)) +
-                      (eyp1 - ey0 - ld<1>(xb, d, k + 1, j - 1, i) + ld<1>(xb, d, k, j - 1, i));
-
-    double sx = D.c, sy = D.c, sz = D.c;
-    if (D.eps_b > 0) {
-      // edge permittivity: mean of the four cells sharing the edge, summed
-      // in the order (-,-), (+,-), (-,+), (+,+) of the two transverse axes
-      if (j >= 1 && k >= 1) {
-        const double e = 0.25 * (((cell_eps(eps, D, i, j - 1, k - 1) + cell_eps(eps, D, i, j - 1, k)) +
-                                  cell_eps(eps, D, i, j, k - 1)) + cell_eps(eps, D, i, j, k));
-        sx = D.c / e;
-      }
-      if (i >= 1 && k >= 1) {
-        const double e = 0.25 * (((cell_eps(eps, D, i - 1, j, k - 1) + cell_eps(eps, D, i - 1, j, k)) +
-                                  cell_eps(eps, D, i, j, k - 1)) + cell_eps(eps, D, i, j, k));
-        sy = D.c / e;
-      }
-      if (i >= 1 && j >= 1) {
-        const double e = 0.25 * (((cell_eps(eps, D, i - 1, j - 1, k) + cell_eps(eps, D, i - 1, j, k)) +
-                                  cell_eps(eps, D, i, j - 1, k)) + cell_eps(eps, D, i, j, k));
-        sz = D.c / e;
-      }
+  // stage plane kk of every component into slot s (zero outside / on walls)
+  auto load_plane = [&](int kk, int s) {
+    for (int e = t; e < 3 * HY * HX; e += TX * TY) {
+      const int q = e / (HY * HX);
+      const int rem = e - q * (HY * HX);
+      const int jj = rem / HX, ii = rem - jj * HX;
+      const int gi = T.x0 - 1 + ii, gj = T.y0 - 1 + jj;
+      bool ok = gi >= 0 && gj >= 0 && kk >= 0 && gi < nx && gj < ny && kk < nz;
+      if (q == 0) ok = ok && gj != 0 && kk != 0;
+      else if (q == 1) ok = ok && gi != 0 && kk != 0;
+      else ok = ok && gi != 0 && gj != 0;
+      P[s][q][jj][ii] = ok ? xb[q * cs + ((long long)kk * ny + gj) * nx + gi] : 0.0;
     }
-    const long long o = ((long long)k * D.ny + j) * D.nx + i;
-    yb[o] = (j == 0 || k == 0) ? 0.0 : ex0 + sx * kx;
-    yb[d.cs + o] = (i == 0 || k == 0) ? 0.0 : ey0 + sy * ky;
-    yb[2 * d.cs + o] = (i == 0 || j == 0) ? 0.0 : ez0 + sz * kz;
+  };
+  auto load_eps = [&](int kk, int s) {
+    const int b = D.eps_b;
+    for (int e = t; e < (TY + 1) * (TX + 1); e += TX * TY) {
+      const int jj = e / (TX + 1), ii = e - jj * (TX + 1);
+      const int gi = min(max(T.x0 - 1 + ii, 0), nx - 1);
+      const int gj = min(max(T.y0 - 1 + jj, 0), ny - 1);
+      const int gk = min(max(kk, 0), nz - 1);
+      E[s][jj][ii] = eps[D.eps_off + ((gk / b) * D.eps_nby + (gj / b)) * D.eps_nbx + (gi / b)];
+    }
+  };
 
-    exm = ex0; ex0 = exp1;
-    eym = ey0; ey0 = eyp1;
-    ezm = ez0;
+  load_plane(k0 - 1, (k0 + 2) % 3);
+  load_plane(k0, k0 % 3);
+  if (use_eps) load_eps(k0 - 1, (k0 + 1) & 1);
+  for (int k = k0; k < k1; ++k) {
+    load_plane(k + 1, (k + 1) % 3);
+    if (use_eps) load_eps(k, k & 1);
+    __syncthreads();
+    const int sm = (k + 2) % 3, s0 = k % 3, sp = (k + 1) % 3;
+    const int a = ty + 1, c = tx + 1;      // own position inside the halo tile
+    const double ex0 = P[s0][0][a][c], ey0 = P[s0][1][a][c], ez0 = P[s0][2][a][c];
+    const double kx = 4.0 * ex0 - P[s0][0][a + 1][c] - P[s0][0][a - 1][c] - P[sp][0][a][c] -
+                      P[sm][0][a][c] +
+                      (P[s0][1][a][c + 1] - ey0 - P[s0][1][a - 1][c + 1] + P[s0][1][a - 1][c]) +
+                      (P[s0][2][a][c + 1] - ez0 - P[sm][2][a][c + 1] + P[sm][2][a][c]);
+    const double ky = 4.0 * ey0 - P[sp][1][a][c] - P[sm][1][a][c] - P[s0][1][a][c + 1] -
+                      P[s0][1][a][c - 1] +
+                      (P[s0][2][a + 1][c] - ez0 - P[sm][2][a + 1][c] + P[sm][2][a][c]) +
+                      (P[s0][0][a + 1][c] - ex0 - P[s0][0][a + 1][c - 1] + P[s0][0][a][c - 1]);
+    const double kz = 4.0 * ez0 - P[s0][2][a][c + 1] - P[s0][2][a][c - 1] - P[s0][2][a + 1][c] -
+                      P[s0][2][a - 1][c] +
+                      (P[sp][0][a][c] - ex0 - P[sp][0][a][c - 1] + P[s0][0][a][c - 1]) +
+                      (P[sp][1][a][c] - ey0 - P[sp][1][a - 1][c] + P[s0][1][a - 1][c]);
+    double sx = D.c, sy = D.c, sz = D.c;
+    if (use_eps) {
+      // edge permittivity: mean of the four cells sharing the edge, summed in
+      // the order (-,-), (+,-), (-,+), (+,+) of the two transverse axes
+      const int em = (k + 1) & 1, e0 = k & 1;   // cell planes k-1 and k
+      const int ja = ty + 1, ia = tx + 1;       // cell (j, i) inside the eps tile
+      sx = D.c / (0.25 * (((E[em][ja - 1][ia] + E[e0][ja - 1][ia]) + E[em][ja][ia]) + E[e0][ja][ia]));
+      sy = D.c / (0.25 * (((E[em][ja][ia - 1] + E[e0][ja][ia - 1]) + E[em][ja][ia]) + E[e0][ja][ia]));
+      sz = D.c / (0.25 * (((E[e0][ja - 1][ia - 1] + E[e0][ja][ia - 1]) + E[e0][ja - 1][ia]) +
+                          E[e0][ja][ia]));
+    }
+    if (i < nx && j < ny) {
+      const long long o = ((long long)k * ny + j) * nx + i;
+      yb[o] = (j == 0 || k == 0) ? 0.0 : ex0 + sx * kx;
+      yb[cs + o] = (i == 0 || k == 0) ? 0.0 : ey0 + sy * ky;
+      yb[2 * cs + o] = (i == 0 || j == 0) ? 0.0 : ez0 + sz * kz;
+    }
+    __syncthreads();
   }
 }
 
@@ -120,8 +128,8 @@ hipError_t launch_curlcurl(const double* x, double* y, const DomainDev* doms,
                            const StencilTile* tiles, int ntiles, const double* eps,
                            hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_curlcurl, dim3(ntiles), dim3(kStencilTX * kStencilTY), 0, s, x, y, doms,
-                     tiles, eps);
+  hipLaunchKernelGGL(k_curlcurl, dim3(ntiles), dim3(TX * TY), 0, s, x, y, doms, tiles, ntiles,
+                     eps);
   return hipGetLastError();
 }
 

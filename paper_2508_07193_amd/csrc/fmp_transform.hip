@@ -38,30 +38,40 @@ __device__ __forceinline__ float fmaT<float>(float a, float b, float c) {
   return __builtin_fmaf(a, b, c);
 }
 
-// o = Tm v  (o[p] = sum_l Tm[p][l] v[l])
-template <typename T, int NP>
-__device__ __forceinline__ void contract_fwd(const T* __restrict__ Tm, const T (&v)[NP],
-                                             T (&o)[NP]) {
+// Contraction out[p] = sum_l M[p][l] v[l] for p < n_out, each result handed to
+// store(p, value).  M is row-major with stride kTS (the forward matrix for a
+// forward transform, the transposed table for an inverse one), so a row is a
+// contiguous run of scalar loads.  The output loop stays rolled: one row of M
+// lives in SGPRs at a time (fully unrolling it makes the compiler hoist every
+// row and spill SGPRs into VGPR lanes).  Two accumulators halve the FMA chain.
+template <typename T, int NP, class Store>
+__device__ __forceinline__ void contract(const T* __restrict__ M, const T (&v)[NP], int n_out,
+                                         Store store) {
+#pragma unroll 1
+  for (int p = 0; p < n_out; ++p) {
+    const T* __restrict__ row = M + p * kTS;
+    T a0 = T(0), a1 = T(0);
 #pragma unroll
-  for (int p = 0; p < NP; ++p) {
-    T acc = T(0);
-#pragma unroll
-    for (int l = 0; l < NP; ++l) acc = fmaT<T>(Tm[p * kTS + l], v[l], acc);
-    o[p] = acc;
+    for (int l = 0; l + 1 < NP; l += 2) {
+      a0 = fmaT<T>(row[l], v[l], a0);
+      a1 = fmaT<T>(row[l + 1], v[l + 1], a1);
+    }
+    if (NP & 1) a0 = fmaT<T>(row[NP - 1], v[NP - 1], a0);
+    store(p, a0 + a1);
   }
 }
 
-// v = Tm^T o  (v[l] = sum_p Tm[p][l] o[p])
-template <typename T, int NP>
-__device__ __forceinline__ void contract_inv(const T* __restrict__ Tm, const T (&o)[NP],
-                                             T (&v)[NP]) {
-#pragma unroll
-  for (int l = 0; l < NP; ++l) {
-    T acc = T(0);
-#pragma unroll
-    for (int p = 0; p < NP; ++p) acc = fmaT<T>(Tm[p * kTS + l], o[p], acc);
-    v[l] = acc;
-  }
+template <typename T>
+__device__ __forceinline__ T recip(T d) {
+  return T(1) / d;
+}
+// 1/d for d >= 1 from the hardware estimate and two Newton steps
+template <>
+__device__ __forceinline__ double recip<double>(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = __builtin_fma(__builtin_fma(-d, r, 1.0), r, r);
+  r = __builtin_fma(__builtin_fma(-d, r, 1.0), r, r);
+  return r;
 }
 
 // slot 0 of a component's node axes is the box wall
@@ -107,16 +117,13 @@ __global__ __launch_bounds__(256) void k_pass_a(const double* __restrict__ r, T*
   }
   __syncthreads();
 
-  T v[NP], o[NP];
+  T v[NP];
   const T* Tx = tab + (q == 0 ? B.dct[0] : B.dst[0]);
   if (t < nzs * ny) {                             // x contraction, one row per lane
     const int zl = t / ny, y = t - zl * ny;
 #pragma unroll
     for (int l = 0; l < NP; ++l) v[l] = (l < nx) ? buf[zl][y][l] : T(0);
-    contract_fwd<T, NP>(Tx, v, o);
-#pragma unroll
-    for (int p = 0; p < NP; ++p)
-      if (p < nx) buf[zl][y][p] = o[p];
+    contract<T, NP>(Tx, v, nx, [&](int p, T val) { buf[zl][y][p] = val; });
   }
   __syncthreads();
 
@@ -125,11 +132,8 @@ __global__ __launch_bounds__(256) void k_pass_a(const double* __restrict__ r, T*
     const int zl = t / nx, x = t - zl * nx;
 #pragma unroll
     for (int m = 0; m < NP; ++m) v[m] = (m < ny) ? buf[zl][m][x] : T(0);
-    contract_fwd<T, NP>(Ty, v, o);
     T* dst = W + B.w_off + (long long)q * B.vol + (long long)(z0 + zl) * plane + x;
-#pragma unroll
-    for (int p = 0; p < NP; ++p)
-      if (p < ny) dst[p * nx] = o[p];
+    contract<T, NP>(Ty, v, ny, [&](int p, T val) { dst[p * nx] = val; });
   }
 }
 
@@ -151,13 +155,13 @@ __global__ __launch_bounds__(192) void k_pass_b(T* __restrict__ W, const BoxDev*
   const bool active = c < plane;
   T* col = W + B.w_off + (long long)q * B.vol + (active ? c : 0);
 
-  T v[NP], o[NP];
+  T v[NP];
 #pragma unroll
   for (int l = 0; l < NP; ++l) v[l] = (active && l < nz) ? col[(long long)l * plane] : T(0);
-  const T* Tz = tab + (q == 2 ? B.dct[2] : B.dst[2]);
-  contract_fwd<T, NP>(Tz, v, o);
-#pragma unroll
-  for (int rr = 0; rr < NP; ++rr) ex[q][rr][lane] = o[rr];
+  const bool own = q == 2;                        // DCT-II along z for E_z, DST-I otherwise
+  const T* Tz = tab + (own ? B.dct[2] : B.dst[2]);
+  const T* TzT = tab + (own ? B.dctT[2] : B.dst[2]);
+  contract<T, NP>(Tz, v, NP, [&](int r, T val) { ex[q][r][lane] = val; });
   __syncthreads();
 
   const int yy = active ? c / nx : 0;
@@ -166,21 +170,18 @@ __global__ __launch_bounds__(192) void k_pass_b(T* __restrict__ W, const BoxDev*
   const T sy = tab[B.sig[1] + yy];
   const T* sz = tab + B.sig[2];
   const T alpha = (T)B.alpha;
+  const T sxy2 = fmaT<T>(sx, sx, sy * sy);
 #pragma unroll
-  for (int rr = 0; rr < NP; ++rr) {
+  for (int rr = 0; rr < NP; ++rr) {               // e = (r + alpha s (s.r)) / (1 + alpha |s|^2)
     const T s3 = sz[rr];
     const T a = ex[0][rr][lane], b = ex[1][rr][lane], d = ex[2][rr][lane];
-    const T s2 = fmaT<T>(sx, sx, fmaT<T>(sy, sy, s3 * s3));
     const T dot = fmaT<T>(sx, a, fmaT<T>(sy, b, s3 * d));
     const T sq = q == 0 ? sx : (q == 1 ? sy : s3);
-    o[rr] = fmaT<T>(alpha * sq, dot, o[rr]) / fmaT<T>(alpha, s2, T(1));
+    const T rq = q == 0 ? a : (q == 1 ? b : d);
+    v[rr] = fmaT<T>(alpha * sq, dot, rq) * recip<T>(fmaT<T>(alpha, fmaT<T>(s3, s3, sxy2), T(1)));
   }
-  contract_inv<T, NP>(Tz, o, v);
-  if (active) {
-#pragma unroll
-    for (int l = 0; l < NP; ++l)
-      if (l < nz) col[(long long)l * plane] = v[l];
-  }
+  if (active)
+    contract<T, NP>(TzT, v, nz, [&](int l, T val) { col[(long long)l * plane] = val; });
 }
 
 // ---------------------------------------------------------------- pass C
@@ -212,27 +213,21 @@ __global__ __launch_bounds__(256) void k_pass_c(const T* __restrict__ W, double*
   }
   __syncthreads();
 
-  T v[NP], o[NP];
-  const T* Ty = tab + (q == 1 ? B.dct[1] : B.dst[1]);
+  T v[NP];
+  const T* TyT = tab + (q == 1 ? B.dctT[1] : B.dst[1]);
   if (t < nzs * nx) {                             // y inverse, one column per lane
     const int zl = t / nx, x = t - zl * nx;
 #pragma unroll
-    for (int m = 0; m < NP; ++m) o[m] = (m < ny) ? buf[zl][m][x] : T(0);
-    contract_inv<T, NP>(Ty, o, v);
-#pragma unroll
-    for (int m = 0; m < NP; ++m)
-      if (m < ny) buf[zl][m][x] = v[m];
+    for (int m = 0; m < NP; ++m) v[m] = (m < ny) ? buf[zl][m][x] : T(0);
+    contract<T, NP>(TyT, v, ny, [&](int m, T val) { buf[zl][m][x] = val; });
   }
   __syncthreads();
-  const T* Tx = tab + (q == 0 ? B.dct[0] : B.dst[0]);
+  const T* TxT = tab + (q == 0 ? B.dctT[0] : B.dst[0]);
   if (t < nzs * ny) {                             // x inverse, one row per lane
     const int zl = t / ny, y = t - zl * ny;
 #pragma unroll
-    for (int p = 0; p < NP; ++p) o[p] = (p < nx) ? buf[zl][y][p] : T(0);
-    contract_inv<T, NP>(Tx, o, v);
-#pragma unroll
-    for (int l = 0; l < NP; ++l)
-      if (l < nx) buf[zl][y][l] = v[l];
+    for (int p = 0; p < NP; ++p) v[p] = (p < nx) ? buf[zl][y][p] : T(0);
+    contract<T, NP>(TxT, v, nx, [&](int l, T val) { buf[zl][y][l] = val; });
   }
   __syncthreads();
 

@@ -1,0 +1,149 @@
+"""GPU parity of the learned coarse correction (restriction, MLP kernels, fallback)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import coarse, ras, yee
+from paper_2508_07193_amd import api, inputs, learned
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def dev(a, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a).ravel()).to(DEV, dtype)
+
+
+def rel2(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
+
+
+def _problem(n=32, sub=8, c=8.0, seed=5):
+    P = inputs.make_problem(dict(n=n, sub=sub, c=c, eps_block=8, seed=seed))
+    h = api.Handle([dict(nx=n, ny=n, nz=n, c=c, eps=P["eps"], eps_block=8, sub=sub)],
+                   use_learned=True, device=DEV)
+    return P, h
+
+
+def test_restrict_matches_oracle():
+    P, h = _problem()
+    n_in = api.fmp_coarse_size(h)
+    assert n_in == 3 * 4 ** 3
+    rc = torch.zeros(n_in, dtype=torch.float64, device=DEV)
+    api.fmp_coarse_restrict(h, dev(P["rhs"]), rc)
+    ref = coarse.restrict(P["rhs"], P["sub"])
+    assert np.abs(rc.cpu().numpy() - ref).max() <= 1e-14 * np.abs(P["rhs"]).max()
+
+
+def test_mlp_gradients_match_fp64_oracle():
+    """bf16 operands, FP32 accumulation: each GEMM carries ~2^-8 relative rounding."""
+    n_in, hidden, batch = 96, 64, 50
+    rng = np.random.default_rng(0)
+    p = learned.init_params(n_in, hidden, seed=1, out_scale=1.0)
+    X = rng.standard_normal((batch, n_in)).astype(np.float32)
+    Y = rng.standard_normal((batch, n_in)).astype(np.float32) * 0.1
+    loss_ref, g_ref = coarse.loss_grad(p.astype(np.float64), X.astype(np.float64),
+                                       Y.astype(np.float64), n_in, hidden)
+    params = dev(p, torch.float32)
+    grads = torch.zeros_like(params)
+    loss = torch.zeros(1, dtype=torch.float32, device=DEV)
+    scratch = torch.empty(api.fmp_mlp_scratch_bytes(n_in, hidden, batch), dtype=torch.uint8,
+                          device=DEV)
+    api.fmp_mlp_loss_grad(n_in, hidden, batch, params, dev(X, torch.float32),
+                          dev(Y, torch.float32), grads, loss, scratch)
+    g = grads.cpu().numpy().astype(np.float64)
+    assert abs(float(loss.item()) - loss_ref) / loss_ref < 2e-2
+    sizes = [hidden * n_in, hidden, hidden * hidden, hidden, n_in * hidden, n_in]
+    o = 0
+    for name, sz in zip(["W1", "b1", "W2", "b2", "W3", "b3"], sizes):
+        err = rel2(g[o:o + sz], g_ref[o:o + sz])
+        print(f"grad {name}: rel err {err:.2e}")
+        assert err < 5e-2, name
+        o += sz
+
+
+def test_adam_matches_oracle():
+    rng = np.random.default_rng(2)
+    p0 = rng.standard_normal(1000).astype(np.float32)
+    g = rng.standard_normal(1000).astype(np.float32)
+    pr, mr, vr = p0.astype(np.float64), np.zeros(1000), np.zeros(1000)
+    params, grads = dev(p0, torch.float32), dev(g, torch.float32)
+    m, v = torch.zeros_like(params), torch.zeros_like(params)
+    for t in (1, 2, 3):
+        api.fmp_mlp_adam(params, grads, m, v, t, 1e-2)
+        pr, mr, vr = coarse.adam(pr, g.astype(np.float64), mr, vr, t, 1e-2)
+    assert np.abs(params.cpu().numpy() - pr).max() < 1e-6
+
+
+def test_learned_precond_matches_oracle():
+    P, h = _problem()
+    n_in, hidden = api.fmp_coarse_size(h), 32
+    p = learned.init_params(n_in, hidden, seed=3, out_scale=1.0)
+    r = dev(P["rhs"])
+    z0 = h.new_vector()
+    h.apply_precond(r, z0)
+    api.fmp_set_coarse_model(h, hidden, p)
+    z1 = h.new_vector()
+    h.apply_precond(r, z1)
+    torch.cuda.synchronize()
+    d_gpu = (z1 - z0).cpu().numpy().reshape(P["rhs"].shape)
+    # oracle with the same bf16-rounded weights (biases stay FP32)
+    pw = p.astype(np.float64).copy()
+    W1, b1, W2, b2, W3, b3 = (np.array(a) for a in coarse.unpack(pw, n_in, hidden))
+    pw = np.concatenate([coarse.bf16_round(W1).ravel(), b1, coarse.bf16_round(W2).ravel(), b2,
+                         coarse.bf16_round(W3).ravel(), b3])
+    d_ref = coarse.correction(P["rhs"], P["sub"], pw, n_in, hidden)
+    assert rel2(d_gpu, d_ref) < 1e-5
+    z_ref = ras.ras_apply(P["rhs"], P["c"], P["sub"], 1, yee.expand_eps(P["eps"], 8, 32, 32, 32))
+    assert rel2(z0.cpu().numpy().reshape(z_ref.shape), z_ref) < 1e-12
+
+
+def test_capture_returns_fgmres_iterates():
+    P, h = _problem(n=16, sub=8, c=2.0)
+    b = dev(P["rhs"])
+    cap = torch.zeros(4, h.length, dtype=torch.float64, device=DEV)
+    x = h.new_vector()
+    info = h.solve(b, x, solver="fgmres", rtol=1e-300, max_iter=4, capture=cap)
+    assert info["iterations"] == 4 and info["status"] == "FMP_NOT_CONVERGED"
+    # the last captured iterate is the returned solution; residuals decrease
+    assert torch.allclose(cap[3], x, rtol=1e-12, atol=1e-14)
+    res = []
+    y = h.new_vector()
+    for k in range(4):
+        h.curlcurl_apply(cap[k], y)
+        res.append(float(torch.linalg.vector_norm(b - y)))
+    assert all(res[i + 1] <= res[i] * (1 + 1e-12) for i in range(3))
+
+
+def test_garbage_model_falls_back_and_converges():
+    P, h = _problem()
+    n_in, hidden = api.fmp_coarse_size(h), 32
+    b = dev(P["rhs"])
+    x = h.new_vector()
+    plain = h.solve(b, x, solver="fgmres", rtol=1e-8, max_iter=300)
+    p = learned.init_params(n_in, hidden, seed=4, out_scale=1.0) * 1e3
+    api.fmp_set_coarse_model(h, hidden, p)
+    x = h.new_vector()
+    info = h.solve(b, x, solver="fgmres", rtol=1e-8, max_iter=300)
+    assert info["status"] == "FMP_OK" and info["rel_residual_true"] <= 1e-8
+    assert info["used_fallback"] >= 1
+    assert info["iterations"] <= plain["iterations"] + 1
+
+
+def test_training_reduces_loss_and_solves():
+    """Small end-to-end run: pairs from the solver, training on the GPU, held-out solves."""
+    P, h = _problem()
+    X, Y = learned.generate_pairs(h, (32, 32, 32), n_rhs=12, per_rhs=5, seed0=1005)
+    assert np.all(np.isfinite(X)) and np.all(np.isfinite(Y))
+    params, hist = learned.train(X, Y, hidden=64, epochs=60, batch=20, lr=1e-3, device=DEV)
+    assert hist[-1] < 0.5 * hist[0]
+    api.fmp_set_coarse_model(h, 64, params)
+    b = dev(inputs.extra_rhs(32, 32, 32, 2005))
+    x = h.new_vector()
+    info = h.solve(b, x, solver="fgmres", rtol=1e-8, max_iter=300)
+    assert info["status"] == "FMP_OK" and info["rel_residual_true"] <= 1e-8
+    api.fmp_set_coarse_model(h, 0, None)
+    x = h.new_vector()
+    plain = h.solve(b, x, solver="fgmres", rtol=1e-8, max_iter=300)
+    print(f"held-out: learned {info['iterations']} it ({info['used_fallback']} fallbacks), "
+          f"plain {plain['iterations']} it")
