@@ -105,7 +105,10 @@ typedef struct {
  * check_every: host convergence check period for BiCGSTAB (>= 1).
  * capture_count, capture: FGMRES only; if capture_count > 0, the iterates
  *   x_1 .. x_capture_count are written to the device buffer capture
- *   (capture_count vectors of fmp_vector_layout length, caller-owned). */
+ *   (capture_count vectors of fmp_vector_layout length, caller-owned).
+ * profile: 1 = record HIP events on the solve's stream around every
+ *   preconditioner apply, operator apply and (FGMRES) orthogonalisation
+ *   kernel, and report the times in fmp_solve_info (adds event overhead). */
 typedef struct {
   int32_t solver;
   int32_t restart;
@@ -115,6 +118,7 @@ typedef struct {
   int32_t check_every;
   int32_t capture_count;
   double* capture;
+  int32_t profile;
 } fmp_solve_opts;
 
 typedef struct {
@@ -124,6 +128,11 @@ typedef struct {
   int32_t used_fallback;       /* applies where the learned part was rejected */
   double rel_residual_true;    /* ||b - A x|| / ||b - A x0|| recomputed       */
   double t_total_ms;
+  /* filled when opts.profile = 1 (kernel time from HIP events, ms; bytes are
+   * the algorithmic HBM bytes of those launches: 8 per element read or written) */
+  double t_precond_ms, t_spmv_ms, t_orth_dot_ms, t_orth_update_ms;
+  double bytes_orth_dot, bytes_orth_update;
+  int32_t n_orth_dot, n_orth_update;
 } fmp_solve_info;
 
 /* Build the subdomain plans for n_domains independent domains.

@@ -31,13 +31,17 @@ class PrecondDesc(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("solver", C.c_int32), ("restart", C.c_int32), ("max_iter", C.c_int32),
                 ("rtol", C.c_double), ("precond", C.c_int32), ("check_every", C.c_int32),
-                ("capture_count", C.c_int32), ("capture", C.c_void_p)]
+                ("capture_count", C.c_int32), ("capture", C.c_void_p), ("profile", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("n_precond", C.c_int32), ("n_spmv", C.c_int32),
                 ("used_fallback", C.c_int32), ("rel_residual_true", C.c_double),
-                ("t_total_ms", C.c_double)]
+                ("t_total_ms", C.c_double), ("t_precond_ms", C.c_double),
+                ("t_spmv_ms", C.c_double), ("t_orth_dot_ms", C.c_double),
+                ("t_orth_update_ms", C.c_double), ("bytes_orth_dot", C.c_double),
+                ("bytes_orth_update", C.c_double), ("n_orth_dot", C.c_int32),
+                ("n_orth_update", C.c_int32)]
 
 
 _lib = None

@@ -131,9 +131,10 @@ def fmp_apply_precond(h, r, z, stream=None):
 
 
 def solve_opts(solver="fgmres", restart=30, max_iter=500, rtol=1e-8, precond=True, check_every=1,
-               capture=None):
+               capture=None, profile=False):
     o = _lib.SolveOpts({"bicgstab": 0, "fgmres": 1}[solver], int(restart), int(max_iter),
-                       float(rtol), int(bool(precond)), int(check_every), 0, None)
+                       float(rtol), int(bool(precond)), int(check_every), 0, None,
+                       int(bool(profile)))
     if capture is not None:   # (count, length) float64 CUDA tensor receiving x_1 .. x_count
         o.capture_count = int(capture.shape[0])
         o.capture = C.c_void_p(capture.data_ptr())
@@ -154,9 +155,15 @@ def fmp_solve(h, b, x, stream=None, raise_on_breakdown=True, **kw):
                      C.byref(info), _stream(stream))
     ok = (0, 1) if raise_on_breakdown else (0, 1, -5)
     _check(st, "fmp_solve", h.h, ok=ok)
-    return dict(status=_lib.STATUS[st], iterations=info.iterations, n_precond=info.n_precond,
-                n_spmv=info.n_spmv, used_fallback=info.used_fallback,
-                rel_residual_true=info.rel_residual_true, t_total_ms=info.t_total_ms)
+    out = dict(status=_lib.STATUS[st], iterations=info.iterations, n_precond=info.n_precond,
+               n_spmv=info.n_spmv, used_fallback=info.used_fallback,
+               rel_residual_true=info.rel_residual_true, t_total_ms=info.t_total_ms)
+    if o.profile:
+        out.update(t_precond_ms=info.t_precond_ms, t_spmv_ms=info.t_spmv_ms,
+                   t_orth_dot_ms=info.t_orth_dot_ms, t_orth_update_ms=info.t_orth_update_ms,
+                   bytes_orth_dot=info.bytes_orth_dot, bytes_orth_update=info.bytes_orth_update,
+                   n_orth_dot=info.n_orth_dot, n_orth_update=info.n_orth_update)
+    return out
 
 
 def release_solver_workspace(h):

@@ -145,22 +145,51 @@ static fmp_status precond_apply(fmp_ctx* h, const double* r, double* z, hipStrea
 static fmp_status precond_launches(fmp_ctx* h, const double* r, double* z, hipStream_t s,
                                    const double* coarse) {
   const int prec = h->prec;
-  for (const Launch& L : h->launches) {
+  // Two or more batches: batch k runs on private stream k % 2 with staging
+  // buffer k % 2, so the gather pass of one batch overlaps the solve passes
+  // of the previous one.  Batches write disjoint parts of z.
+  const bool two = h->launches.size() > 1 && h->d_Wb;
+  hipStream_t bs[2] = {s, s};
+  if (two) {
+    for (int i = 0; i < 2; ++i)
+      if (!h->bat_stream[i])
+        HIPCHK(h, hipStreamCreateWithFlags(&h->bat_stream[i], hipStreamNonBlocking));
+    if (!h->ev_fork) {
+      HIPCHK(h, hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+      HIPCHK(h, hipEventCreateWithFlags(&h->ev_join[0], hipEventDisableTiming));
+      HIPCHK(h, hipEventCreateWithFlags(&h->ev_join[1], hipEventDisableTiming));
+    }
+    HIPCHK(h, hipEventRecord(h->ev_fork, s));
+    for (int i = 0; i < 2; ++i) {
+      HIPCHK(h, hipStreamWaitEvent(h->bat_stream[i], h->ev_fork, 0));
+      bs[i] = h->bat_stream[i];
+    }
+  }
+  for (size_t k = 0; k < h->launches.size(); ++k) {
+    const Launch& L = h->launches[k];
+    const hipStream_t st = bs[k & 1];
+    void* W = (two && (k & 1)) ? h->d_Wb : h->d_W;
     if (prec == FMP_BF16) {
-      HIPCHK(h, launch_mfma_pass_a(L.cls, r, (float*)h->d_W, h->d_boxes, h->d_doms,
-                                   h->d_work_a + L.a0, L.na, (const __hip_bfloat16*)h->d_tab, s));
-      HIPCHK(h, launch_mfma_pass_b(L.cls, (float*)h->d_W, h->d_boxes, h->d_work_b + L.b0, L.nb,
-                                   (const __hip_bfloat16*)h->d_tab, h->d_sig32, s));
-      HIPCHK(h, launch_mfma_pass_c(L.cls, (const float*)h->d_W, z, h->d_boxes, h->d_doms,
+      HIPCHK(h, launch_mfma_pass_a(L.cls, r, W, h->d_boxes, h->d_doms,
+                                   h->d_work_a + L.a0, L.na, (const __hip_bfloat16*)h->d_tab, st));
+      HIPCHK(h, launch_mfma_pass_b(L.cls, W, h->d_boxes, h->d_work_b + L.b0, L.nb,
+                                   (const __hip_bfloat16*)h->d_tab, h->d_sig32, st));
+      HIPCHK(h, launch_mfma_pass_c(L.cls, W, z, h->d_boxes, h->d_doms,
                                    h->d_work_a + L.a0, L.na, (const __hip_bfloat16*)h->d_tab,
-                                   coarse, h->nsub, s));
+                                   coarse, h->nsub, st));
     } else {
-      HIPCHK(h, launch_pass_a(prec, L.cls, r, h->d_W, h->d_boxes, h->d_doms, h->d_work_a + L.a0,
-                              L.na, h->d_tab, s));
-      HIPCHK(h, launch_pass_b(prec, L.cls, h->d_W, h->d_boxes, h->d_work_b + L.b0, L.nb,
-                              h->d_tab, s));
-      HIPCHK(h, launch_pass_c(prec, L.cls, h->d_W, z, h->d_boxes, h->d_doms, h->d_work_a + L.a0,
-                              L.na, h->d_tab, coarse, h->nsub, s));
+      HIPCHK(h, launch_pass_a(prec, L.cls, r, W, h->d_boxes, h->d_doms, h->d_work_a + L.a0,
+                              L.na, h->d_tab, st));
+      HIPCHK(h, launch_pass_b(prec, L.cls, W, h->d_boxes, h->d_work_b + L.b0, L.nb,
+                              h->d_tab, st));
+      HIPCHK(h, launch_pass_c(prec, L.cls, W, z, h->d_boxes, h->d_doms, h->d_work_a + L.a0,
+                              L.na, h->d_tab, coarse, h->nsub, st));
+    }
+  }
+  if (two) {
+    for (int i = 0; i < 2; ++i) {
+      HIPCHK(h, hipEventRecord(h->ev_join[i], bs[i]));
+      HIPCHK(h, hipStreamWaitEvent(s, h->ev_join[i], 0));
     }
   }
   return FMP_OK;
@@ -290,7 +319,9 @@ fmp_status fmp_setup_subdomains(const fmp_domain_desc* domains, int32_t n_domain
   int nsides = 0;
   for (int n = 2; n <= kMaxSide; ++n)
     if (sides_used[n]) side_slot[n] = nsides++;
-  const long long per_side = 3LL * kTS * kTS + kTS;   // dct, dct^T, dst, sig
+  // per side: dct, dct^T, dst (kTS x kTS), sig (kTS), then butterfly half
+  // tables for DCT-II and DST-I (4 of kHS x kHS each: TS, TD, TS^T, TD^T)
+  const long long per_side = 3LL * kTS * kTS + kTS + 8LL * kHS * kHS;
   std::vector<double> tab64((size_t)(per_side * nsides), 0.0);
   {
     std::vector<double> c, s, g;
@@ -303,6 +334,22 @@ fmp_status fmp_setup_subdomains(const fmp_domain_desc* domains, int32_t n_domain
         for (int j = 0; j < kTS; ++j) base[kTS * kTS + i * kTS + j] = c[j * kTS + i];
       std::copy(s.begin(), s.end(), base + 2 * kTS * kTS);
       std::copy(g.begin(), g.end(), base + 3 * kTS * kTS);
+      for (int tau = 0; tau < 2; ++tau) {
+        const std::vector<double>& T = tau == 0 ? c : s;   // full n x n matrix, stride kTS
+        double* hb = base + 3 * kTS * kTS + kTS + tau * 4 * kHS * kHS;
+        const int P = (n - tau) / 2, mid = (n - tau) & 1, cm = (n - 1 + tau) / 2;
+        for (int k = 0; k < P + mid; ++k) {
+          for (int j = 0; j < P; ++j) hb[k * kHS + j] = T[(tau + 2 * k) * kTS + tau + j];
+          if (mid) hb[k * kHS + P] = T[(tau + 2 * k) * kTS + cm];
+        }
+        for (int k = 0; k < P; ++k)
+          for (int j = 0; j < P; ++j) hb[kHS * kHS + k * kHS + j] = T[(tau + 2 * k + 1) * kTS + tau + j];
+        for (int i = 0; i < kHS; ++i)
+          for (int j = 0; j < kHS; ++j) {
+            hb[2 * kHS * kHS + i * kHS + j] = hb[j * kHS + i];
+            hb[3 * kHS * kHS + i * kHS + j] = hb[kHS * kHS + j * kHS + i];
+          }
+      }
     }
   }
   if (!h->precond_ok) h->boxes.clear();   // stencil and unpreconditioned solves only
@@ -314,6 +361,8 @@ fmp_status fmp_setup_subdomains(const fmp_domain_desc* domains, int32_t n_domain
       B.dctT[a] = base + kTS * kTS;
       B.dst[a] = base + 2 * kTS * kTS;
       B.sig[a] = base + 3 * kTS * kTS;
+      B.half[a][0] = base + 3 * kTS * kTS + kTS;
+      B.half[a][1] = base + 3 * kTS * kTS + kTS + 4 * kHS * kHS;
       const int mbase = side_slot[sides[a]] * 3 * kTB * kTB;
       B.mdct[a] = mbase;
       B.mdctT[a] = mbase + kTB * kTB;
@@ -384,7 +433,7 @@ fmp_status fmp_setup_subdomains(const fmp_domain_desc* domains, int32_t n_domain
 
   // ---- workspace layout
   const size_t tsz = (h->prec == FMP_FP64) ? 8 : (h->prec == FMP_FP32 ? 4 : 2);
-  const size_t wsz = (h->prec == FMP_FP64) ? 8 : 4;
+  const size_t wsz = (h->prec == FMP_FP64) ? 8 : (h->prec == FMP_FP32 ? 4 : 2);
   size_t cur = 0;
   const size_t o_doms = cur; cur = align_up(cur + h->doms.size() * sizeof(DomainDev));
   const size_t o_boxes = cur; cur = align_up(cur + h->boxes.size() * sizeof(BoxDev));
@@ -400,6 +449,9 @@ fmp_status fmp_setup_subdomains(const fmp_domain_desc* domains, int32_t n_domain
   const size_t o_learn = cur;
   if (h->use_learned) cur = align_up(cur + fmp_coarse_workspace(h->nsub, 512));
   const size_t o_W = cur; cur = align_up(cur + (size_t)w_batch_max * wsz);
+  const bool two_w = h->launches.size() > 1;
+  const size_t o_W2 = cur;
+  if (two_w) cur = align_up(cur + (size_t)w_batch_max * wsz);
   const size_t need = cur;
 
   if (!ws) {
@@ -421,6 +473,7 @@ fmp_status fmp_setup_subdomains(const fmp_domain_desc* domains, int32_t n_domain
   h->d_part = (double*)(base + o_part);
   h->d_S = (double*)(base + o_S);
   h->d_W = base + o_W;
+  if (two_w) h->d_Wb = base + o_W2;
   if (h->use_learned) fmp_coarse_bind(h.get(), base + o_learn);
 
   // typed tables
@@ -467,6 +520,11 @@ fmp_status fmp_destroy(fmp_handle h) {
   if (h->h_S) (void)hipHostFree(h->h_S);
   for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.exec);
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+  for (int i = 0; i < 2; ++i) {
+    if (h->bat_stream[i]) (void)hipStreamDestroy(h->bat_stream[i]);
+    if (h->ev_join[i]) (void)hipEventDestroy(h->ev_join[i]);
+  }
+  if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
   delete h;
   return FMP_OK;
 }
@@ -509,16 +567,77 @@ fmp_status fmp_solve_workspace(fmp_handle h, const fmp_solve_opts* o, size_t* by
 // ============================================================== solvers
 namespace {
 
+// Event timing of kernel classes for opts.profile.  Pairs are recorded
+// around launches and read back at the solver's next synchronisation.
+struct Prof {
+  enum { PRE = 0, SPMV = 1, DOT = 2, UPD = 3 };
+  std::vector<hipEvent_t> pool;
+  struct Pending {
+    int cls;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pend;
+  size_t used = 0;
+  hipEvent_t get() {
+    if (used == pool.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+  ~Prof() {
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  }
+};
+
 struct Ctx {
   fmp_ctx* h;
   hipStream_t s;
   const fmp_solve_opts* o;
   fmp_solve_info* info;
+  Prof* prof;
+  // bracket a launch sequence with events when profiling
+  hipEvent_t begin() {
+    if (!prof) return nullptr;
+    hipEvent_t e = prof->get();
+    if (e) (void)hipEventRecord(e, s);
+    return e;
+  }
+  void end(int cls, hipEvent_t a) {
+    if (!prof || !a) return;
+    hipEvent_t b = prof->get();
+    if (!b) return;
+    (void)hipEventRecord(b, s);
+    prof->pend.push_back({cls, a, b});
+  }
+  // after a synchronisation: accumulate the recorded pairs
+  void harvest() {
+    if (!prof) return;
+    for (const auto& p : prof->pend) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, p.a, p.b) != hipSuccess) continue;
+      double* t = p.cls == Prof::PRE    ? &info->t_precond_ms
+                  : p.cls == Prof::SPMV ? &info->t_spmv_ms
+                  : p.cls == Prof::DOT  ? &info->t_orth_dot_ms
+                                        : &info->t_orth_update_ms;
+      *t += ms;
+    }
+    prof->pend.clear();
+    prof->used = 0;
+  }
 };
 
 // z = M^{-1} r; the learned coarse correction is added only where the caller
 // can judge it (FGMRES), since BiCGSTAB assumes a fixed linear preconditioner.
+fmp_status M_(Ctx& c, const double* r, double* z, bool learned);
 fmp_status M(Ctx& c, const double* r, double* z, bool learned = false) {
+  hipEvent_t e = c.begin();
+  const fmp_status st = M_(c, r, z, learned);
+  c.end(Prof::PRE, e);
+  return st;
+}
+fmp_status M_(Ctx& c, const double* r, double* z, bool learned) {
   c.info->n_precond++;
   if (c.o->precond == 0) {
     HIPCHK(c.h, launch_scale_copy(r, 1.0, z, c.h->len, c.s));
@@ -534,7 +653,29 @@ fmp_status M(Ctx& c, const double* r, double* z, bool learned = false) {
 
 fmp_status A(Ctx& c, const double* x, double* y) {
   c.info->n_spmv++;
-  return spmv(c.h, x, y, c.s);
+  hipEvent_t e = c.begin();
+  const fmp_status st = spmv(c.h, x, y, c.s);
+  c.end(Prof::SPMV, e);
+  return st;
+}
+
+// profiled CGS kernels: h = V^T w (+ ||w||^2), then w -= V h (+ ||w||^2)
+hipError_t orth_dot(Ctx& c, const double* V, long long ldv, int nv, const double* w) {
+  hipEvent_t e = c.begin();
+  const hipError_t r = launch_mdot(V, ldv, nv, w, c.h->len, c.h->d_part, c.s);
+  c.end(Prof::DOT, e);
+  c.info->n_orth_dot++;
+  c.info->bytes_orth_dot += 8.0 * (double)c.h->len * (nv + 1);
+  return r;
+}
+hipError_t orth_update(Ctx& c, const double* V, long long ldv, int nv, const double* hcoef,
+                       double* w) {
+  hipEvent_t e = c.begin();
+  const hipError_t r = launch_mupdate(V, ldv, nv, hcoef, w, c.h->len, c.h->d_part, c.s);
+  c.end(Prof::UPD, e);
+  c.info->n_orth_update++;
+  c.info->bytes_orth_update += 8.0 * (double)c.h->len * (nv + 2);
+  return r;
 }
 
 // r = b - A x into r (tmp used for A x), returns ||r||^2 through the host mirror
@@ -660,22 +801,24 @@ fmp_status fgmres(Ctx& c, const double* b, double* x, double* ws) {
         }
       }
       // classical Gram-Schmidt: h = V^T w (and ||w||^2), w -= V h, ||w||^2
-      HIPCHK(h, launch_mdot(V, (long long)vb, j + 1, w, n, h->d_part, c.s));
+      HIPCHK(h, orth_dot(c, V, (long long)vb, j + 1, w));
       HIPCHK(h, launch_reduce(h->d_part, j + 2, h->d_S + kScalH, 0, h->d_S, c.s));
-      HIPCHK(h, launch_mupdate(V, (long long)vb, j + 1, h->d_S + kScalH, w, n, h->d_part, c.s));
+      HIPCHK(h, orth_update(c, V, (long long)vb, j + 1, h->d_S + kScalH, w));
       HIPCHK(h, launch_reduce(h->d_part, 1, h->d_S + kScalW, 0, h->d_S, c.s));
       HIPCHK(h, hipMemcpyAsync(hs, h->d_S, kScal * 8, hipMemcpyDeviceToHost, c.s));
       HIPCHK(h, hipStreamSynchronize(c.s));
+      c.harvest();
       std::vector<double> hcol(hs + kScalH, hs + kScalH + j + 1);
       const double wn0 = sqrt(hs[kScalH + j + 1]);
       double hn = sqrt(hs[kScalW]);
       if (hn < 0.1 * wn0) {   // second CGS pass
-        HIPCHK(h, launch_mdot(V, (long long)vb, j + 1, w, n, h->d_part, c.s));
+        HIPCHK(h, orth_dot(c, V, (long long)vb, j + 1, w));
         HIPCHK(h, launch_reduce(h->d_part, j + 2, h->d_S + kScalH, 0, h->d_S, c.s));
-        HIPCHK(h, launch_mupdate(V, (long long)vb, j + 1, h->d_S + kScalH, w, n, h->d_part, c.s));
+        HIPCHK(h, orth_update(c, V, (long long)vb, j + 1, h->d_S + kScalH, w));
         HIPCHK(h, launch_reduce(h->d_part, 1, h->d_S + kScalW, 0, h->d_S, c.s));
         HIPCHK(h, hipMemcpyAsync(hs, h->d_S, kScal * 8, hipMemcpyDeviceToHost, c.s));
         HIPCHK(h, hipStreamSynchronize(c.s));
+        c.harvest();
         for (int i = 0; i <= j; ++i) hcol[i] += hs[kScalH + i];
         hn = sqrt(hs[kScalW]);
       }
@@ -747,10 +890,12 @@ extern "C" fmp_status fmp_solve(fmp_handle h, const double* b, double* x, const 
   if (ws_bytes < need || ((uintptr_t)ws) % kAlign) return FMP_ERR_WORKSPACE;
   if (o->precond && !h->precond_ok) return FMP_ERR_UNSUPPORTED;
   fmp_solve_info local{};
-  Ctx c{h, (hipStream_t)stream, o, &local};
+  Prof prof;
+  Ctx c{h, (hipStream_t)stream, o, &local, o->profile ? &prof : nullptr};
   const auto t0 = std::chrono::steady_clock::now();
   st = (o->solver == 0) ? bicgstab(c, b, x, (double*)ws) : fgmres(c, b, x, (double*)ws);
   if (hipStreamSynchronize(c.s) != hipSuccess && st >= 0) st = FMP_ERR_HIP;
+  c.harvest();
   local.t_total_ms =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   if (info) *info = local;

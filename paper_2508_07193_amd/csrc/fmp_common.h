@@ -16,6 +16,7 @@ namespace fmp {
 // every transform table (tables are stored kTS x kTS, zero padded).
 constexpr int kMaxSide = 48;
 constexpr int kTS = 48;
+constexpr int kHS = 24;   // stride of the half (butterfly) tables
 
 // Transform size classes: a box of largest side n runs the kernels compiled
 // for the smallest class >= n (zero-padded rows/columns cost flops only).
@@ -47,6 +48,7 @@ struct BoxDev {
   int sub;              // global subdomain index (coarse vector entry)
   int dct[3], dctT[3], dst[3], sig[3];
   int mdct[3], mdctT[3], mdst[3];   // bf16 tables (row stride 64) of the MFMA passes
+  int half[3][2];       // butterfly half tables per axis: [a][0] DCT-II, [a][1] DST-I
   long long w_off;      // staging offset (elements) of component 0
   long long vol;        // nx*ny*nz
   double alpha;         // c / mean eps over the owned block
@@ -80,14 +82,14 @@ hipError_t launch_pass_c(int prec, int cls, const void* W, double* z, const BoxD
                          const double* coarse, int nsub, hipStream_t s);
 int pass_a_zslab(int cls);   // planes per pass-A/C work item for a class
 
-// BF16 MFMA transform passes (staging in FP32).
-hipError_t launch_mfma_pass_a(int cls, const double* r, float* W, const BoxDev* boxes,
+// BF16 MFMA transform passes (staging W in bf16).
+hipError_t launch_mfma_pass_a(int cls, const double* r, void* W, const BoxDev* boxes,
                               const DomainDev* doms, const int4* work, int nwork,
                               const __hip_bfloat16* tab, hipStream_t s);
-hipError_t launch_mfma_pass_b(int cls, float* W, const BoxDev* boxes, const int4* work,
+hipError_t launch_mfma_pass_b(int cls, void* W, const BoxDev* boxes, const int4* work,
                               int nwork, const __hip_bfloat16* tab, const float* sig,
                               hipStream_t s);
-hipError_t launch_mfma_pass_c(int cls, const float* W, double* z, const BoxDev* boxes,
+hipError_t launch_mfma_pass_c(int cls, const void* W, double* z, const BoxDev* boxes,
                               const DomainDev* doms, const int4* work, int nwork,
                               const __hip_bfloat16* tab, const double* coarse, int nsub,
                               hipStream_t s);

@@ -65,6 +65,10 @@ struct fmp_ctx {
   };
   bool use_graph = false;
   hipStream_t cap_stream = nullptr;
+  // batches alternate between two private streams and two staging buffers
+  void* d_Wb = nullptr;
+  hipStream_t bat_stream[2] = {nullptr, nullptr};
+  hipEvent_t ev_fork = nullptr, ev_join[2] = {nullptr, nullptr};
   std::vector<Graph> graphs;
   std::string err;
 };

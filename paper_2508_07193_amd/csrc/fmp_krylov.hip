@@ -59,43 +59,73 @@ __global__ __launch_bounds__(kThreads) void k_dots(DotPtrs P, int n, long long l
   block_store<8>(acc, n, partials);
 }
 
+// Multi-vector kernels.  They are instantiated for the exact number of basis
+// vectors (1..33): an unrolled loop guarded by a runtime count issues its
+// loads in small groups and loses about a quarter of the bandwidth.  Each
+// thread walks 16-byte pairs of doubles with a grid stride; a trailing odd
+// element is handled by thread 0 of the last block.
+typedef double dbl2 __attribute__((ext_vector_type(2)));
+
+// basis vectors are streamed once per pass: non-temporal loads
+__device__ __forceinline__ dbl2 ld_stream(const double* __restrict__ base, long long p) {
+  return __builtin_nontemporal_load(reinterpret_cast<const dbl2*>(base) + p);
+}
+
 template <int NV>
 __global__ __launch_bounds__(kThreads) void k_mdot(const double* __restrict__ V, long long ldv,
-                                                   int nv, const double* __restrict__ w,
-                                                   long long len, double* __restrict__ partials) {
+                                                   const double* __restrict__ w, long long len,
+                                                   double* __restrict__ partials) {
   double acc[NV + 1];
 #pragma unroll
   for (int i = 0; i <= NV; ++i) acc[i] = 0.0;
-  const long long stride = (long long)kRedBlocks * kThreads;
-  for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < len; e += stride) {
+  const long long np = len >> 1, stride = (long long)gridDim.x * kThreads;
+  const dbl2* __restrict__ w2 = reinterpret_cast<const dbl2*>(w);
+  for (long long p = (long long)blockIdx.x * kThreads + threadIdx.x; p < np; p += stride) {
+    const dbl2 we = w2[p];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const dbl2 v = ld_stream(V + i * ldv, p);
+      acc[i] = __builtin_fma(v.x, we.x, __builtin_fma(v.y, we.y, acc[i]));
+    }
+    acc[NV] = __builtin_fma(we.x, we.x, __builtin_fma(we.y, we.y, acc[NV]));
+  }
+  if ((len & 1) && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+    const long long e = len - 1;
     const double we = w[e];
 #pragma unroll
-    for (int i = 0; i < NV; ++i)
-      if (i < nv) acc[i] = __builtin_fma(V[i * ldv + e], we, acc[i]);
+    for (int i = 0; i < NV; ++i) acc[i] = __builtin_fma(V[i * ldv + e], we, acc[i]);
     acc[NV] = __builtin_fma(we, we, acc[NV]);
   }
-  // move <w,w> to slot nv so that partial columns are 0..nv
-  double out[NV + 1];
-#pragma unroll
-  for (int i = 0; i <= NV; ++i) out[i] = (i < nv) ? acc[i] : (i == nv ? acc[NV] : 0.0);
-  block_store<NV + 1>(out, nv + 1, partials);
+  block_store<NV + 1>(acc, NV + 1, partials);   // <w,w> lands in column NV
 }
 
 template <int NV>
 __global__ __launch_bounds__(kThreads) void k_mupdate(const double* __restrict__ V, long long ldv,
-                                                      int nv, const double* __restrict__ h,
+                                                      const double* __restrict__ h,
                                                       double* __restrict__ w, long long len,
                                                       double* __restrict__ partials) {
   double hh[NV];
 #pragma unroll
-  for (int i = 0; i < NV; ++i) hh[i] = (i < nv) ? h[i] : 0.0;
+  for (int i = 0; i < NV; ++i) hh[i] = h[i];
   double acc[1] = {0.0};
-  const long long stride = (long long)kRedBlocks * kThreads;
-  for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < len; e += stride) {
+  const long long np = len >> 1, stride = (long long)gridDim.x * kThreads;
+  dbl2* __restrict__ w2 = reinterpret_cast<dbl2*>(w);
+  for (long long p = (long long)blockIdx.x * kThreads + threadIdx.x; p < np; p += stride) {
+    dbl2 we = w2[p];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const dbl2 v = reinterpret_cast<const dbl2*>(V + i * ldv)[p];
+      we.x = __builtin_fma(-hh[i], v.x, we.x);
+      we.y = __builtin_fma(-hh[i], v.y, we.y);
+    }
+    w2[p] = we;
+    acc[0] = __builtin_fma(we.x, we.x, __builtin_fma(we.y, we.y, acc[0]));
+  }
+  if ((len & 1) && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+    const long long e = len - 1;
     double we = w[e];
 #pragma unroll
-    for (int i = 0; i < NV; ++i)
-      if (i < nv) we = __builtin_fma(-hh[i], V[i * ldv + e], we);
+    for (int i = 0; i < NV; ++i) we = __builtin_fma(-hh[i], V[i * ldv + e], we);
     w[e] = we;
     acc[0] = __builtin_fma(we, we, acc[0]);
   }
@@ -104,8 +134,37 @@ __global__ __launch_bounds__(kThreads) void k_mupdate(const double* __restrict__
 
 template <int NV>
 __global__ __launch_bounds__(kThreads) void k_xupdate(const double* __restrict__ Z, long long ldz,
-                                                      int nz, const double* __restrict__ y,
+                                                      const double* __restrict__ y,
                                                       double* __restrict__ x, long long len) {
+  double yy[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) yy[i] = y[i];
+  const long long np = len >> 1, stride = (long long)gridDim.x * kThreads;
+  dbl2* __restrict__ x2 = reinterpret_cast<dbl2*>(x);
+  for (long long p = (long long)blockIdx.x * kThreads + threadIdx.x; p < np; p += stride) {
+    dbl2 xe = x2[p];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const dbl2 v = ld_stream(Z + i * ldz, p);
+      xe.x = __builtin_fma(yy[i], v.x, xe.x);
+      xe.y = __builtin_fma(yy[i], v.y, xe.y);
+    }
+    x2[p] = xe;
+  }
+  if ((len & 1) && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+    const long long e = len - 1;
+    double xe = x[e];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) xe = __builtin_fma(yy[i], Z[i * ldz + e], xe);
+    x[e] = xe;
+  }
+}
+
+// same update for operands that are not 16-byte aligned
+template <int NV>
+__global__ __launch_bounds__(kThreads) void k_xupdate1(const double* __restrict__ Z, long long ldz,
+                                                       int nz, const double* __restrict__ y,
+                                                       double* __restrict__ x, long long len) {
   double yy[NV];
 #pragma unroll
   for (int i = 0; i < NV; ++i) yy[i] = (i < nz) ? y[i] : 0.0;
@@ -232,6 +291,41 @@ int grid_for(long long len) {
   return (int)g;
 }
 
+// compile-time dispatch of a runtime basis count to its instantiation
+template <int N>
+struct NV {
+  static void mdot(int nv, const double* V, long long ldv, const double* w, long long len,
+                   double* part, hipStream_t s) {
+    if (nv == N)
+      hipLaunchKernelGGL((k_mdot<N>), dim3(kRedBlocks), dim3(kThreads), 0, s, V, ldv, w, len, part);
+    else
+      NV<N - 1>::mdot(nv, V, ldv, w, len, part, s);
+  }
+  static void mupdate(int nv, const double* V, long long ldv, const double* h, double* w,
+                      long long len, double* part, hipStream_t s) {
+    if (nv == N)
+      hipLaunchKernelGGL((k_mupdate<N>), dim3(kRedBlocks), dim3(kThreads), 0, s, V, ldv, h, w, len,
+                         part);
+    else
+      NV<N - 1>::mupdate(nv, V, ldv, h, w, len, part, s);
+  }
+  static void xupdate(int nz, const double* Z, long long ldz, const double* y, double* x,
+                      long long len, hipStream_t s) {
+    if (nz == N)
+      hipLaunchKernelGGL((k_xupdate<N>), dim3(kRedBlocks), dim3(kThreads), 0, s, Z, ldz, y, x, len);
+    else
+      NV<N - 1>::xupdate(nz, Z, ldz, y, x, len, s);
+  }
+};
+template <>
+struct NV<0> {
+  static void mdot(int, const double*, long long, const double*, long long, double*, hipStream_t) {}
+  static void mupdate(int, const double*, long long, const double*, double*, long long, double*,
+                      hipStream_t) {}
+  static void xupdate(int, const double*, long long, const double*, double*, long long,
+                      hipStream_t) {}
+};
+
 }  // namespace
 
 hipError_t launch_dots(const DotPtrs& p, int n, long long len, double* partials, hipStream_t s) {
@@ -243,12 +337,7 @@ hipError_t launch_dots(const DotPtrs& p, int n, long long len, double* partials,
 hipError_t launch_mdot(const double* V, long long ldv, int nv, const double* w, long long len,
                        double* partials, hipStream_t s) {
   if (nv < 1 || nv + 1 > kMaxDots) return hipErrorInvalidValue;
-#define L(NV) hipLaunchKernelGGL((k_mdot<NV>), dim3(kRedBlocks), dim3(kThreads), 0, s, V, ldv, nv, w, len, partials)
-  if (nv <= 4) L(4);
-  else if (nv <= 8) L(8);
-  else if (nv <= 16) L(16);
-  else L(33);
-#undef L
+  NV<33>::mdot(nv, V, ldv, w, len, partials, s);
   return hipGetLastError();
 }
 
@@ -262,24 +351,24 @@ hipError_t launch_reduce(const double* partials, int n, double* out, int post, d
 hipError_t launch_mupdate(const double* V, long long ldv, int nv, const double* h, double* w,
                           long long len, double* partials, hipStream_t s) {
   if (nv < 1 || nv > 33) return hipErrorInvalidValue;
-#define L(NV) hipLaunchKernelGGL((k_mupdate<NV>), dim3(kRedBlocks), dim3(kThreads), 0, s, V, ldv, nv, h, w, len, partials)
-  if (nv <= 4) L(4);
-  else if (nv <= 8) L(8);
-  else if (nv <= 16) L(16);
-  else L(33);
-#undef L
+  NV<33>::mupdate(nv, V, ldv, h, w, len, partials, s);
   return hipGetLastError();
 }
 
 hipError_t launch_xupdate(const double* Z, long long ldz, int nz, const double* y, double* x,
                           long long len, hipStream_t s) {
   if (nz < 1 || nz > 33) return hipErrorInvalidValue;
-#define L(NV) hipLaunchKernelGGL((k_xupdate<NV>), dim3(grid_for(len)), dim3(kThreads), 0, s, Z, ldz, nz, y, x, len)
-  if (nz <= 4) L(4);
-  else if (nz <= 8) L(8);
-  else if (nz <= 16) L(16);
-  else L(33);
+  const bool aligned = ((uintptr_t)Z % 16 == 0) && ((uintptr_t)x % 16 == 0) && (ldz % 2 == 0);
+  if (aligned) {
+    NV<33>::xupdate(nz, Z, ldz, y, x, len, s);
+  } else {
+#define L(NVV) hipLaunchKernelGGL((k_xupdate1<NVV>), dim3(grid_for(len)), dim3(kThreads), 0, s, Z, ldz, nz, y, x, len)
+    if (nz <= 4) L(4);
+    else if (nz <= 8) L(8);
+    else if (nz <= 16) L(16);
+    else L(33);
 #undef L
+  }
   return hipGetLastError();
 }
 

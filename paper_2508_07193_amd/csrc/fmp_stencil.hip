@@ -54,9 +54,18 @@ __global__ __launch_bounds__(TX * TY) void k_curlcurl(const double* __restrict__
   const int k0 = T.z0, k1 = min(T.z0 + kStencilZC, nz);
   const bool use_eps = D.eps_b > 0;
 
-  // stage plane kk of every component into slot s (zero outside / on walls)
-  auto load_plane = [&](int kk, int s) {
-    for (int e = t; e < 3 * HY * HX; e += TX * TY) {
+  // Plane staging is software-pipelined: a thread holds its share of plane
+  // k+2 (and of the cell-eps plane k+1) in registers, loaded while plane k is
+  // being computed, and commits it to LDS after the step's barrier.
+  constexpr int NE = (3 * HY * HX + TX * TY - 1) / (TX * TY);
+  constexpr int NEE = ((TY + 1) * (TX + 1) + TX * TY - 1) / (TX * TY);
+  double pre[NE], epre[NEE];
+  unsigned ok_mask = 0;
+  auto fetch = [&](int kk) {
+    ok_mask = 0;
+#pragma unroll
+    for (int i = 0; i < NE; ++i) {
+      const int e = min(t + i * TX * TY, 3 * HY * HX - 1);
       const int q = e / (HY * HX);
       const int rem = e - q * (HY * HX);
       const int jj = rem / HX, ii = rem - jj * HX;
@@ -65,27 +74,57 @@ __global__ __launch_bounds__(TX * TY) void k_curlcurl(const double* __restrict__
       if (q == 0) ok = ok && gj != 0 && kk != 0;
       else if (q == 1) ok = ok && gi != 0 && kk != 0;
       else ok = ok && gi != 0 && gj != 0;
-      P[s][q][jj][ii] = ok ? xb[q * cs + ((long long)kk * ny + gj) * nx + gi] : 0.0;
+      if (ok) ok_mask |= 1u << i;
+      const int ci = min(max(gi, 0), nx - 1), cj = min(max(gj, 0), ny - 1);
+      const int ck = min(max(kk, 0), nz - 1);
+      pre[i] = xb[q * cs + ((long long)ck * ny + cj) * nx + ci];
     }
   };
-  auto load_eps = [&](int kk, int s) {
+  auto commit = [&](int s) {
+#pragma unroll
+    for (int i = 0; i < NE; ++i) {
+      const int e = t + i * TX * TY;
+      if (e < 3 * HY * HX) (&P[s][0][0][0])[e] = ((ok_mask >> i) & 1u) ? pre[i] : 0.0;
+    }
+  };
+  auto fetch_eps = [&](int kk) {
     const int b = D.eps_b;
-    for (int e = t; e < (TY + 1) * (TX + 1); e += TX * TY) {
+#pragma unroll
+    for (int i = 0; i < NEE; ++i) {
+      const int e = min(t + i * TX * TY, (TY + 1) * (TX + 1) - 1);
       const int jj = e / (TX + 1), ii = e - jj * (TX + 1);
       const int gi = min(max(T.x0 - 1 + ii, 0), nx - 1);
       const int gj = min(max(T.y0 - 1 + jj, 0), ny - 1);
       const int gk = min(max(kk, 0), nz - 1);
-      E[s][jj][ii] = eps[D.eps_off + ((gk / b) * D.eps_nby + (gj / b)) * D.eps_nbx + (gi / b)];
+      epre[i] = eps[D.eps_off + ((gk / b) * D.eps_nby + (gj / b)) * D.eps_nbx + (gi / b)];
+    }
+  };
+  auto commit_eps = [&](int s) {
+#pragma unroll
+    for (int i = 0; i < NEE; ++i) {
+      const int e = t + i * TX * TY;
+      if (e < (TY + 1) * (TX + 1)) (&E[s][0][0])[e] = epre[i];
     }
   };
 
-  load_plane(k0 - 1, (k0 + 2) % 3);
-  load_plane(k0, k0 % 3);
-  if (use_eps) load_eps(k0 - 1, (k0 + 1) & 1);
+  fetch(k0 - 1);
+  commit((k0 + 2) % 3);
+  fetch(k0);
+  commit(k0 % 3);
+  if (use_eps) {
+    fetch_eps(k0 - 1);
+    commit_eps((k0 + 1) & 1);
+    fetch_eps(k0);
+  }
+  fetch(k0 + 1);
   for (int k = k0; k < k1; ++k) {
-    load_plane(k + 1, (k + 1) % 3);
-    if (use_eps) load_eps(k, k & 1);
+    commit((k + 1) % 3);
+    if (use_eps) commit_eps(k & 1);
     __syncthreads();
+    if (k + 1 < k1) {                            // prefetch the next step's planes
+      fetch(k + 2);
+      if (use_eps) fetch_eps(k + 1);
+    }
     const int sm = (k + 2) % 3, s0 = k % 3, sp = (k + 1) % 3;
     const int a = ty + 1, c = tx + 1;      // own position inside the halo tile
     const double ex0 = P[s0][0][a][c], ey0 = P[s0][1][a][c], ez0 = P[s0][2][a][c];

@@ -38,27 +38,95 @@ __device__ __forceinline__ float fmaT<float>(float a, float b, float c) {
   return __builtin_fmaf(a, b, c);
 }
 
-// Contraction out[p] = sum_l M[p][l] v[l] for p < n_out, each result handed to
-// store(p, value).  M is row-major with stride kTS (the forward matrix for a
-// forward transform, the transposed table for an inverse one), so a row is a
-// contiguous run of scalar loads.  The output loop stays rolled: one row of M
-// lives in SGPRs at a time (fully unrolling it makes the compiler hoist every
-// row and spill SGPRs into VGPR lanes).  Two accumulators halve the FMA chain.
-template <typename T, int NP, class Store>
-__device__ __forceinline__ void contract(const T* __restrict__ M, const T (&v)[NP], int n_out,
-                                         Store store) {
-#pragma unroll 1
-  for (int p = 0; p < n_out; ++p) {
-    const T* __restrict__ row = M + p * kTS;
-    T a0 = T(0), a1 = T(0);
+// One butterfly stage of the DCT-II / DST-I symmetry.  Both transforms pair
+// the input index l with n-1-l: for DCT-II, T[p][n-1-l] = (-1)^p T[p][l]
+// (pairs l = 0..P-1, base 0); for DST-I on slots 1..n-1, T[m][n-l] =
+// (-1)^(m+1) T[m][l] (pairs l = 1..P, base 1).  With a_j = base + j,
+// b_j = n-1-j, P = (n-base)/2 pairs and a middle index c = (n-1+base)/2 when
+// n - base is odd:
+//   sums  S_j = x[a_j] + x[b_j] (and S_P = x[c]) feed outputs base + 2k,
+//   diffs D_j = x[a_j] - x[b_j]                 feed outputs base + 2k + 1,
+// so a length-n transform is two half-size products.  The inverse (T^T) uses
+// the same half tables transposed: E_j +- O_j give x[a_j] and x[b_j].
+// Half tables per (side, type), each kHS x kHS, zero padded:
+//   TS[k][j], TD[k][j] (forward rows), TS^T, TD^T (inverse rows).
+struct Half {
+  int n, base, P, mid, c;
+};
+
+__device__ __forceinline__ Half half_geom(int n, int tau) {
+  Half g;
+  g.n = n;
+  g.base = tau;
+  g.P = (n - tau) >> 1;
+  g.mid = (n - tau) & 1;
+  g.c = (n - 1 + tau) >> 1;
+  return g;
+}
+
+// dot of a scalar-loaded table row with a register vector (two accumulators)
+template <typename T, int NH>
+__device__ __forceinline__ T row_dot(const T* __restrict__ row, const T (&v)[NH]) {
+  T a0 = T(0), a1 = T(0);
 #pragma unroll
-    for (int l = 0; l + 1 < NP; l += 2) {
-      a0 = fmaT<T>(row[l], v[l], a0);
-      a1 = fmaT<T>(row[l + 1], v[l + 1], a1);
-    }
-    if (NP & 1) a0 = fmaT<T>(row[NP - 1], v[NP - 1], a0);
-    store(p, a0 + a1);
+  for (int j = 0; j + 1 < NH; j += 2) {
+    a0 = fmaT<T>(row[j], v[j], a0);
+    a1 = fmaT<T>(row[j + 1], v[j + 1], a1);
   }
+  if (NH & 1) a0 = fmaT<T>(row[NH - 1], v[NH - 1], a0);
+  return a0 + a1;
+}
+
+// forward: y = T x; x read through ld(index), y written through st(index, value).
+// Output loops stay rolled so one table row at a time sits in SGPRs.
+template <typename T, int NH, class Load, class Store>
+__device__ __forceinline__ void fwd_bfly(const T* __restrict__ tab, const Half g, Load ld,
+                                         Store st) {
+  T sv[NH], dv[NH];
+#pragma unroll
+  for (int j = 0; j < NH; ++j) {
+    T xa = T(0), xb = T(0);
+    if (j < g.P) {
+      xa = ld(g.base + j);
+      xb = ld(g.n - 1 - j);
+    } else if (j == g.P && g.mid) {
+      xa = ld(g.c);
+    }
+    sv[j] = xa + xb;
+    dv[j] = xa - xb;
+  }
+  const T* __restrict__ TS = tab;
+  const T* __restrict__ TD = tab + kHS * kHS;
+  const int NS = g.P + g.mid;
+#pragma unroll 1
+  for (int k = 0; k < NS; ++k) st(g.base + 2 * k, row_dot<T, NH>(TS + k * kHS, sv));
+#pragma unroll 1
+  for (int k = 0; k < g.P; ++k) st(g.base + 2 * k + 1, row_dot<T, NH>(TD + k * kHS, dv));
+  if (g.base) st(0, T(0));                        // DST-I: slot 0 holds no mode
+}
+
+// inverse: x = T^T y
+template <typename T, int NH, class Load, class Store>
+__device__ __forceinline__ void inv_bfly(const T* __restrict__ tab, const Half g, Load ld,
+                                         Store st) {
+  T ys[NH], yd[NH];
+  const int NS = g.P + g.mid;
+#pragma unroll
+  for (int k = 0; k < NH; ++k) {
+    ys[k] = (k < NS) ? ld(g.base + 2 * k) : T(0);
+    yd[k] = (k < g.P) ? ld(g.base + 2 * k + 1) : T(0);
+  }
+  const T* __restrict__ TSt = tab + 2 * kHS * kHS;
+  const T* __restrict__ TDt = tab + 3 * kHS * kHS;
+#pragma unroll 1
+  for (int j = 0; j < g.P; ++j) {
+    const T e = row_dot<T, NH>(TSt + j * kHS, ys);
+    const T o = row_dot<T, NH>(TDt + j * kHS, yd);
+    st(g.base + j, e + o);
+    st(g.n - 1 - j, e - o);
+  }
+  if (g.mid) st(g.c, row_dot<T, NH>(TSt + g.P * kHS, ys));
+  if (g.base) st(0, T(0));                        // DST-I: the wall slot
 }
 
 template <typename T>
@@ -79,20 +147,35 @@ __device__ __forceinline__ bool box_wall(int q, int x, int y, int z) {
   return q == 0 ? (y == 0 || z == 0) : (q == 1 ? (x == 0 || z == 0) : (x == 0 || y == 0));
 }
 
+// e / d for 0 <= e < 2^24 from a precomputed 1/d: the rounding error of
+// (e + 1/2) / d in FP64 is far below the 1/(2d) margin to the next integer.
+__device__ __forceinline__ int qdiv(int e, double inv_d) { return (int)(((double)e + 0.5) * inv_d); }
+
+// Passes A and C run 128-thread workgroups over slabs of 128/NP planes: the
+// FP64 slab then needs ~28 KB of LDS (5 workgroups per CU instead of 2 with
+// 256 threads), which is what hides the gather latency.
+constexpr int kAC = 128;
 template <int NP>
 constexpr int zslab() {
-  return 256 / NP;
+  return kAC / NP;
 }
+
+// Slabs live in LDS densely as [zl][y][x] with the box's own strides, so a
+// slab element's LDS index is its linear index e.  Loads of a thread are all
+// issued before any is consumed (addresses clamped in bounds, results
+// selected afterwards): the kernels are latency-bound otherwise.
 
 // ---------------------------------------------------------------- pass A
 template <typename T, int NP>
-__global__ __launch_bounds__(256) void k_pass_a(const double* __restrict__ r, T* __restrict__ W,
+__global__ __launch_bounds__(kAC) void k_pass_a(const double* __restrict__ r, T* __restrict__ W,
                                                 const BoxDev* __restrict__ boxes,
                                                 const DomainDev* __restrict__ doms,
                                                 const int4* __restrict__ work,
                                                 const T* __restrict__ tab) {
   constexpr int ZS = zslab<NP>();
-  __shared__ T buf[ZS][NP][NP + 1];
+  constexpr int MAXE = (ZS * NP * NP + kAC - 1) / kAC;
+  constexpr int NH = NP / 2;
+  __shared__ T buf[ZS * NP * NP];
   const int4 wk = work[blockIdx.x];
   const BoxDev& B = boxes[wk.x];
   const int q = wk.y, z0 = wk.z;
@@ -103,37 +186,37 @@ __global__ __launch_bounds__(256) void k_pass_a(const double* __restrict__ r, T*
   const int plane = ny * nx;
   const int tot = nzs * plane;
   const int t = threadIdx.x;
+  const double inv_plane = 1.0 / plane, inv_nx = 1.0 / nx;
 
-  for (int e = t; e < tot; e += 256) {          // S^gamma: gather the slab
-    const int zl = e / plane;
-    const int rem = e - zl * plane;
-    const int y = rem / nx;
-    const int x = rem - y * nx;
-    const int lz = z0 + zl;
-    T val = T(0);
-    if (!box_wall(q, x, y, lz))
-      val = (T)src[((long long)(B.bz0 + lz) * D.ny + (B.by0 + y)) * D.nx + (B.bx0 + x)];
-    buf[zl][y][x] = val;
-  }
-  __syncthreads();
-
-  T v[NP];
-  const T* Tx = tab + (q == 0 ? B.dct[0] : B.dst[0]);
-  if (t < nzs * ny) {                             // x contraction, one row per lane
-    const int zl = t / ny, y = t - zl * ny;
+  double vals[MAXE];                              // S^gamma: gather the slab
+  unsigned wall = 0;
 #pragma unroll
-    for (int l = 0; l < NP; ++l) v[l] = (l < nx) ? buf[zl][y][l] : T(0);
-    contract<T, NP>(Tx, v, nx, [&](int p, T val) { buf[zl][y][p] = val; });
+  for (int i = 0; i < MAXE; ++i) {
+    const int e = min(t + kAC * i, tot - 1);
+    const int zl = qdiv(e, inv_plane), rem = e - zl * plane;
+    const int y = qdiv(rem, inv_nx), x = rem - y * nx;
+    if (box_wall(q, x, y, z0 + zl)) wall |= 1u << i;
+    vals[i] = src[((B.bz0 + z0 + zl) * D.ny + (B.by0 + y)) * D.nx + (B.bx0 + x)];
+  }
+#pragma unroll
+  for (int i = 0; i < MAXE; ++i) {
+    const int e = t + kAC * i;
+    if (e < tot) buf[e] = ((wall >> i) & 1u) ? T(0) : (T)vals[i];
   }
   __syncthreads();
 
-  const T* Ty = tab + (q == 1 ? B.dct[1] : B.dst[1]);
-  if (t < nzs * nx) {                             // y contraction, one column per lane
+  if (t < nzs * ny) {                             // x, one row per lane (in place)
+    T* row = buf + t * nx;
+    fwd_bfly<T, NH>(tab + B.half[0][q == 0 ? 0 : 1], half_geom(nx, q == 0 ? 0 : 1),
+                    [&](int l) { return row[l]; }, [&](int p, T v) { row[p] = v; });
+  }
+  __syncthreads();
+  if (t < nzs * nx) {                             // y, one column per lane, to the staging
     const int zl = t / nx, x = t - zl * nx;
-#pragma unroll
-    for (int m = 0; m < NP; ++m) v[m] = (m < ny) ? buf[zl][m][x] : T(0);
+    const T* colp = buf + zl * plane + x;
     T* dst = W + B.w_off + (long long)q * B.vol + (long long)(z0 + zl) * plane + x;
-    contract<T, NP>(Ty, v, ny, [&](int p, T val) { dst[p * nx] = val; });
+    fwd_bfly<T, NH>(tab + B.half[1][q == 1 ? 0 : 1], half_geom(ny, q == 1 ? 0 : 1),
+                    [&](int m) { return colp[m * nx]; }, [&](int p, T v) { dst[p * nx] = v; });
   }
 }
 
@@ -142,11 +225,12 @@ template <typename T, int NP>
 __global__ __launch_bounds__(192) void k_pass_b(T* __restrict__ W, const BoxDev* __restrict__ boxes,
                                                 const int4* __restrict__ work,
                                                 const T* __restrict__ tab) {
+  constexpr int NH = NP / 2;
   __shared__ T ex[3][NP][64];
   const int4 wk = work[blockIdx.x];
   const BoxDev& B = boxes[wk.x];
   // one wave per component; readfirstlane tells the compiler q is wave-uniform,
-  // so the matrix entries below stay scalar operands
+  // so the table entries below stay scalar operands
   const int q = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int lane = threadIdx.x & 63;
   const int nx = B.nx, ny = B.ny, nz = B.nz;
@@ -155,13 +239,16 @@ __global__ __launch_bounds__(192) void k_pass_b(T* __restrict__ W, const BoxDev*
   const bool active = c < plane;
   T* col = W + B.w_off + (long long)q * B.vol + (active ? c : 0);
 
-  T v[NP];
+  T v[NP];                                        // the column, all loads in flight
 #pragma unroll
-  for (int l = 0; l < NP; ++l) v[l] = (active && l < nz) ? col[(long long)l * plane] : T(0);
-  const bool own = q == 2;                        // DCT-II along z for E_z, DST-I otherwise
-  const T* Tz = tab + (own ? B.dct[2] : B.dst[2]);
-  const T* TzT = tab + (own ? B.dctT[2] : B.dst[2]);
-  contract<T, NP>(Tz, v, NP, [&](int r, T val) { ex[q][r][lane] = val; });
+  for (int l = 0; l < NP; ++l) v[l] = col[(long long)min(l, nz - 1) * plane];
+#pragma unroll
+  for (int l = 0; l < NP; ++l) ex[q][l][lane] = v[l];
+  const int tz = q == 2 ? 0 : 1;                  // DCT-II along z for E_z, DST-I otherwise
+  const T* tabz = tab + B.half[2][tz];
+  const Half gz = half_geom(nz, tz);
+  fwd_bfly<T, NH>(tabz, gz, [&](int l) { return ex[q][l][lane]; },
+                  [&](int r, T val) { ex[q][r][lane] = val; });
   __syncthreads();
 
   const int yy = active ? c / nx : 0;
@@ -180,20 +267,27 @@ __global__ __launch_bounds__(192) void k_pass_b(T* __restrict__ W, const BoxDev*
     const T rq = q == 0 ? a : (q == 1 ? b : d);
     v[rr] = fmaT<T>(alpha * sq, dot, rq) * recip<T>(fmaT<T>(alpha, fmaT<T>(s3, s3, sxy2), T(1)));
   }
-  if (active)
-    contract<T, NP>(TzT, v, nz, [&](int l, T val) { col[(long long)l * plane] = val; });
+  __syncthreads();                                // every wave has read all three components
+#pragma unroll
+  for (int rr = 0; rr < NP; ++rr) ex[q][rr][lane] = v[rr];
+  inv_bfly<T, NH>(tabz, gz, [&](int r) { return ex[q][r][lane]; },
+                  [&](int l, T val) {
+                    if (active) col[(long long)l * plane] = val;
+                  });
 }
 
 // ---------------------------------------------------------------- pass C
 template <typename T, int NP>
-__global__ __launch_bounds__(256) void k_pass_c(const T* __restrict__ W, double* __restrict__ z,
+__global__ __launch_bounds__(kAC) void k_pass_c(const T* __restrict__ W, double* __restrict__ z,
                                                 const BoxDev* __restrict__ boxes,
                                                 const DomainDev* __restrict__ doms,
                                                 const int4* __restrict__ work,
                                                 const T* __restrict__ tab,
                                                 const double* __restrict__ coarse, int nsub) {
   constexpr int ZS = zslab<NP>();
-  __shared__ T buf[ZS][NP][NP + 1];
+  constexpr int MAXE = (ZS * NP * NP + kAC - 1) / kAC;
+  constexpr int NH = NP / 2;
+  __shared__ T buf[ZS * NP * NP];
   const int4 wk = work[blockIdx.x];
   const BoxDev& B = boxes[wk.x];
   const int q = wk.y, z0 = wk.z;
@@ -204,30 +298,25 @@ __global__ __launch_bounds__(256) void k_pass_c(const T* __restrict__ W, double*
   const int t = threadIdx.x;
   const T* srcw = W + B.w_off + (long long)q * B.vol + (long long)z0 * plane;
 
-  for (int e = t; e < tot; e += 256) {
-    const int zl = e / plane;
-    const int rem = e - zl * plane;
-    const int y = rem / nx;
-    const int x = rem - y * nx;
-    buf[zl][y][x] = srcw[e];
-  }
+  T vals[MAXE];                                   // the staged slab is contiguous
+#pragma unroll
+  for (int i = 0; i < MAXE; ++i) vals[i] = srcw[min(t + kAC * i, tot - 1)];
+#pragma unroll
+  for (int i = 0; i < MAXE; ++i)
+    if (t + kAC * i < tot) buf[t + kAC * i] = vals[i];
   __syncthreads();
 
-  T v[NP];
-  const T* TyT = tab + (q == 1 ? B.dctT[1] : B.dst[1]);
-  if (t < nzs * nx) {                             // y inverse, one column per lane
+  if (t < nzs * nx) {                             // y inverse, one column per lane (in place)
     const int zl = t / nx, x = t - zl * nx;
-#pragma unroll
-    for (int m = 0; m < NP; ++m) v[m] = (m < ny) ? buf[zl][m][x] : T(0);
-    contract<T, NP>(TyT, v, ny, [&](int m, T val) { buf[zl][m][x] = val; });
+    T* colp = buf + zl * plane + x;
+    inv_bfly<T, NH>(tab + B.half[1][q == 1 ? 0 : 1], half_geom(ny, q == 1 ? 0 : 1),
+                    [&](int m) { return colp[m * nx]; }, [&](int m, T v) { colp[m * nx] = v; });
   }
   __syncthreads();
-  const T* TxT = tab + (q == 0 ? B.dctT[0] : B.dst[0]);
-  if (t < nzs * ny) {                             // x inverse, one row per lane
-    const int zl = t / ny, y = t - zl * ny;
-#pragma unroll
-    for (int p = 0; p < NP; ++p) v[p] = (p < nx) ? buf[zl][y][p] : T(0);
-    contract<T, NP>(TxT, v, nx, [&](int l, T val) { buf[zl][y][l] = val; });
+  if (t < nzs * ny) {                             // x inverse, one row per lane (in place)
+    T* row = buf + t * nx;
+    inv_bfly<T, NH>(tab + B.half[0][q == 0 ? 0 : 1], half_geom(nx, q == 0 ? 0 : 1),
+                    [&](int p) { return row[p]; }, [&](int l, T v) { row[l] = v; });
   }
   __syncthreads();
 
@@ -240,23 +329,24 @@ __global__ __launch_bounds__(256) void k_pass_c(const T* __restrict__ W, double*
   const DomainDev& D = doms[B.dom];
   double* dst = z + D.offset + (long long)q * D.nz * D.ny * D.nx;
   const double cq = coarse ? coarse[(long long)q * nsub + B.sub] : 0.0;
-  for (int e = t; e < otot; e += 256) {
-    const int zl = e / oplane;
+  const double inv_op = 1.0 / oplane, inv_sx = 1.0 / B.sx;
+  for (int e = t; e < otot; e += kAC) {
+    const int zl = qdiv(e, inv_op);
     const int rem = e - zl * oplane;
-    const int y = rem / B.sx;
+    const int y = qdiv(rem, inv_sx);
     const int x = rem - y * B.sx;
     const int lz = lz0 + zl, ly = ly0 + y, lx = lx0 + x;
     const int gz = B.bz0 + lz, gy = B.by0 + ly, gx = B.bx0 + lx;
-    double val = (double)buf[lz - z0][ly][lx];
+    double val = (double)buf[(lz - z0) * plane + ly * nx + lx];
     if (coarse && !box_wall(q, gx, gy, gz)) val += cq;
-    dst[((long long)gz * D.ny + gy) * D.nx + gx] = val;
+    dst[(gz * D.ny + gy) * D.nx + gx] = val;
   }
 }
 
 template <typename T, int NP>
 hipError_t run_a(const double* r, void* W, const BoxDev* boxes, const DomainDev* doms,
                  const int4* work, int nwork, const void* tab, hipStream_t s) {
-  hipLaunchKernelGGL((k_pass_a<T, NP>), dim3(nwork), dim3(256), 0, s, r, (T*)W, boxes, doms, work,
+  hipLaunchKernelGGL((k_pass_a<T, NP>), dim3(nwork), dim3(kAC), 0, s, r, (T*)W, boxes, doms, work,
                      (const T*)tab);
   return hipGetLastError();
 }
@@ -271,7 +361,7 @@ template <typename T, int NP>
 hipError_t run_c(const void* W, double* z, const BoxDev* boxes, const DomainDev* doms,
                  const int4* work, int nwork, const void* tab, const double* coarse, int nsub,
                  hipStream_t s) {
-  hipLaunchKernelGGL((k_pass_c<T, NP>), dim3(nwork), dim3(256), 0, s, (const T*)W, z, boxes, doms,
+  hipLaunchKernelGGL((k_pass_c<T, NP>), dim3(nwork), dim3(kAC), 0, s, (const T*)W, z, boxes, doms,
                      work, (const T*)tab, coarse, nsub);
   return hipGetLastError();
 }
@@ -291,7 +381,7 @@ hipError_t run_c(const void* W, double* z, const BoxDev* boxes, const DomainDev*
 
 }  // namespace
 
-int pass_a_zslab(int cls) { return 256 / kClasses[cls]; }
+int pass_a_zslab(int cls) { return kAC / kClasses[cls]; }
 
 hipError_t launch_pass_a(int prec, int cls, const double* r, void* W, const BoxDev* boxes,
                          const DomainDev* doms, const int4* work, int nwork, const void* tab,

@@ -12,6 +12,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def _header_symbols():
     src = open(os.path.join(ROOT, "include", "flashmp.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)       # declarations only, not comments
     return sorted(set(re.findall(r"\b(fmp_[a-z0-9_]+)\s*\(", src)))
 
 

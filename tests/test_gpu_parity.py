@@ -314,3 +314,43 @@ def test_precond_graph_replay_matches_eager():
     x = h.new_vector()
     info = h.solve(r, x, solver="fgmres", rtol=1e-8, max_iter=200)
     assert info["status"] == "FMP_OK"
+
+
+def test_odd_length_vectors():
+    """15^3 grid (odd vector length 10125): tails of the pair-wise vector kernels."""
+    P = problem(15, 5, 2.0, 5, seed=13)
+    A, Af, Mf = _oracle_ops(P)
+    _, io = krylov.fgmres(Af, P["rhs"], M=Mf, tol=1e-8)
+    h = handle_for(P)
+    assert h.length % 2 == 1
+    x = h.new_vector()
+    cap = torch.zeros(3, h.length, dtype=torch.float64, device=DEV)   # odd-offset slots
+    info = h.solve(dev(P["rhs"]), x, solver="fgmres", rtol=1e-8, max_iter=300, capture=cap)
+    assert info["status"] == "FMP_OK" and abs(info["iterations"] - io["iterations"]) <= 1
+    xs = host(x, P["rhs"].shape)
+    res = np.linalg.norm(yee.from_padded(P["rhs"]) - A @ yee.from_padded(xs)) / np.linalg.norm(P["rhs"])
+    assert res <= 1.5e-8
+    assert torch.isfinite(cap).all()
+
+
+def test_batch_of_uneven_domains_matches_oracle():
+    """Several independent domains of different sizes and c in one handle (one apply)."""
+    rng = np.random.default_rng(21)
+    spec = [(24, 24, 1.5), (16, 16, 0.5), (12, 12, 8.0), (48, 24, 3.0)]   # (n, sub, c)
+    doms, rhs = [], []
+    for n, sub, c in spec:
+        doms.append(dict(nx=n, ny=n, nz=n, c=c, sub=sub))
+        rhs.append(inputs.normal_rhs(rng, n, n, n))
+    for prec, tol in (("fp64", 1e-12), ("fp32", 2e-5)):
+        h = api.Handle(doms, precision=prec, device=DEV)
+        r = torch.cat([dev(v) for v in rhs])
+        z = h.new_vector()
+        h.apply_precond(r, z)
+        out = z.cpu().numpy()
+        for d, ((n, sub, c), v) in enumerate(zip(spec, rhs)):
+            ref = ras.ras_apply(v, c, (sub,) * 3, 1)
+            got = out[h.offsets[d]:h.offsets[d + 1]].reshape(ref.shape)
+            assert relmax(got, ref) < tol, (prec, d)
+    x = h.new_vector()
+    info = h.solve(r, x, solver="fgmres", rtol=1e-8, max_iter=300)
+    assert info["status"] == "FMP_OK" and info["rel_residual_true"] <= 1e-8
