@@ -24,6 +24,33 @@ METRIC = ("time-to-solution at rel. residual 1e-8 (256³) + precond applies/s; "
           "plain vs mixed/learned")
 HBM_PEAK_GBS = 8000.0
 
+# HBM traffic of each roofline kernel as a multiple of its algorithmic bytes,
+# from rocprofv3 FETCH_SIZE / WRITE_SIZE runs of this bench on the 256^3
+# workload (KiB per dispatch, scaled by a plain in-place scale of one vector:
+# FETCH x2.000, WRITE x1.000).  A ratio holds only for the kernel sources it
+# was measured on: if any listed source changed since, traffic is null.
+TRAFFIC = {
+    "k_mupdate": (1.0000, {"fmp_krylov.hip": "b605955e21ab53cd3a1b2791b328b879484d8b111c435f98e7516558b66cb171"}),
+    "k_mdot": (1.0000, {"fmp_krylov.hip": "b605955e21ab53cd3a1b2791b328b879484d8b111c435f98e7516558b66cb171"}),
+    "k_curlcurl": (1.0729, {"fmp_stencil.hip": "1513c873efb6702a2f91e867f0820d685c6e24d499270475f779a056e79f98e2"}),
+    "precond_apply": (4.100, {"fmp_transform.hip": "1488a8003c092fe35ca78da18e8ef8ea34e31f43e3be4d6032ace881387999b7",
+                              "fmp_api.hip": "0e0e3233cd16aa25024f2a2da0f91e17b4f2c44547aff657dacbea0e7fe3ccdb"}),
+}
+
+
+def traffic_ratio(name):
+    import hashlib
+    ratio, srcs = TRAFFIC[name]
+    d = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2508_07193_amd", "csrc")
+    for f, h in srcs.items():
+        try:
+            with open(os.path.join(d, f), "rb") as fh:
+                if hashlib.sha256(fh.read()).hexdigest() != h:
+                    return None
+        except OSError:
+            return None
+    return ratio
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -122,19 +149,23 @@ def learned_leg(args, dev, log):
 def batch_leg(args, dev, log):
     """64 independent cubic domains, sides from {24,32,48,64,96}, c ~ U[0.5,8] (seed 4).
 
-    One handle holds all domains; the preconditioner apply covers every box of
-    every domain (FP32 transforms) and FGMRES(30) runs in FP64 on the
-    concatenated vector to 1e-8.  The per-domain relative residuals of the
-    result are reported as well.
+    One handle holds all domains; a preconditioner apply covers every box of
+    every domain (FP32 transforms) as one hipGraph replay.  The timed solve is
+    an independent FGMRES(30) per domain in FP64 to 1e-8, all domains advanced
+    in lockstep through shared launches; each domain's residual is recomputed
+    here as well.  One FGMRES on the concatenated system is reported beside it.
     """
     import torch
     from paper_2508_07193_amd import api, inputs
     doms_in = inputs.make_batch_c4()
     doms = [dict(nx=d["nx"], ny=d["ny"], nz=d["nz"], c=d["c"], sub=d["sub"]) for d in doms_in]
-    h = api.Handle(doms, overlap=1, precision="fp32", device=dev, use_graph=True)
+    h = api.Handle(doms, overlap=1, precision="fp32", device=dev, use_graph=True, batch_boxes=-1)
     b = torch.cat([torch.from_numpy(d["rhs"].ravel()) for d in doms_in]).to(dev)
     n_unk = sum(inputs.n_unknowns(d["nx"], d["ny"], d["nz"]) for d in doms_in)
     z = h.new_vector()
+    tune = h.autotune(b, z)
+    chosen = [t for t in tune if t["chosen"]][0]
+    log(f"[batch] autotune: {[(t['batch_boxes'], t['streams'], round(t['apply_ms'], 3)) for t in tune]}")
     h.apply_precond(b, z)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -143,27 +174,46 @@ def batch_leg(args, dev, log):
     torch.cuda.synchronize()
     t_pre = (time.perf_counter() - t0) / 10 * 1e3
     x = h.new_vector()
-    h.solve(b, x, solver="fgmres", rtol=1e-8, max_iter=500)
-    x.zero_()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    info = h.solve(b, x, solver="fgmres", rtol=1e-8, max_iter=500)
-    torch.cuda.synchronize()
-    tts = (time.perf_counter() - t0) * 1e3
     y = h.new_vector()
-    h.curlcurl_apply(x, y)
-    rel = []
-    for d in range(len(doms)):
-        a, e = h.offsets[d], h.offsets[d + 1]
-        rel.append(float(torch.linalg.vector_norm(b[a:e] - y[a:e]) / torch.linalg.vector_norm(b[a:e])))
+
+    def timed(per_domain):
+        x.zero_()
+        h.solve(b, x, solver="fgmres", rtol=1e-8, max_iter=500, per_domain=per_domain)
+        x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = h.solve(b, x, solver="fgmres", rtol=1e-8, max_iter=500, per_domain=per_domain)
+        torch.cuda.synchronize()
+        tts = (time.perf_counter() - t0) * 1e3
+        h.curlcurl_apply(x, y)
+        rel = []
+        for d in range(len(doms)):
+            a, e = h.offsets[d], h.offsets[d + 1]
+            rel.append(float(torch.linalg.vector_norm(b[a:e] - y[a:e]) / torch.linalg.vector_norm(b[a:e])))
+        return info, tts, rel
+
+    info_c, tts_c, rel_c = timed(False)
+    info, tts, rel = timed(True)
+    its = sorted(info["domain_iterations"])
     sides = [d["nx"] for d in doms_in]
-    log(f"[batch] {info} tts {tts:.1f} ms, precond {t_pre:.3f} ms, max domain rel res {max(rel):.2e}")
+    log(f"[batch] independent: status {info['status']} lockstep steps {info['iterations']}, "
+        f"per-domain steps {its}, tts {tts:.1f} ms, max domain rel res {max(rel):.2e}; "
+        f"concatenated: {info_c['iterations']} steps, tts {tts_c:.1f} ms, max domain rel res "
+        f"{max(rel_c):.2e}; precond {t_pre:.3f} ms")
     return dict(workload="64 cubic domains, sides U{24,32,48,64,96} (seed 4), c ~ U[0.5,8], eps 1; "
-                         "FP32 transforms, FGMRES(30) FP64 to 1e-8 on the concatenated system",
+                         "FP32 transforms; independent FGMRES(30) per domain, FP64, to 1e-8 each",
                 unknowns=n_unk, side_counts={str(k): sides.count(k) for k in sorted(set(sides))},
-                time_to_solution_ms=round(tts, 2), iterations=info["iterations"],
-                rel_residual_true=info["rel_residual_true"], max_domain_rel_residual=max(rel),
+                time_to_solution_ms=round(tts, 2), lockstep_steps=info["iterations"],
+                domain_steps_min_median_max=[its[0], its[len(its) // 2], its[-1]],
+                max_domain_rel_residual=max(rel),
+                max_domain_rel_residual_solver=max(info["domain_rel_residual"]),
+                concatenated_system=dict(time_to_solution_ms=round(tts_c, 2),
+                                         iterations=info_c["iterations"],
+                                         max_domain_rel_residual=max(rel_c)),
                 precond_applies_per_s=round(1e3 / t_pre, 1), precond_ms=round(t_pre, 4),
+                autotune=dict(chosen=dict(batch_boxes=chosen["batch_boxes"], streams=chosen["streams"]),
+                              candidates=[[t["batch_boxes"], t["streams"], round(t["apply_ms"], 4)]
+                                          for t in tune]),
                 launch="hipGraph replay of the per-class, per-batch pass sequence")
 
 
@@ -236,10 +286,13 @@ def main():
     y = h.new_vector()
     t_pre = time_events(lambda: h.apply_precond(b, z), 10)
     t_spmv = time_events(lambda: h.curlcurl_apply(b, y), 20)
-    def roof(kernel, bytes_per_launch, avg_ms, per):
+    def roof(name, kernel, bytes_per_launch, avg_ms, per):
         ach = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+        ratio = traffic_ratio(name)
         return dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(ach / HBM_PEAK_GBS, 3), traffic=None, kernel=kernel,
+                    frac=round(ach / HBM_PEAK_GBS, 3),
+                    traffic=None if ratio is None else round(ratio * bytes_per_launch),
+                    kernel=kernel,
                     bytes_per_launch=round(bytes_per_launch), avg_ms=round(avg_ms, 4),
                     algorithmic_bytes=per)
 
@@ -249,17 +302,17 @@ def main():
     log(f"[fp64 profiled] {pinfo}")
     spmv_bytes = 16.0 * n_unk
     roofs = {
-        "k_mupdate": roof("k_mupdate (CGS: w -= V h, ||w||^2)",
+        "k_mupdate": roof("k_mupdate", "k_mupdate (CGS: w -= V h, ||w||^2)",
                           pinfo["bytes_orth_update"] / pinfo["n_orth_update"],
                           pinfo["t_orth_update_ms"] / pinfo["n_orth_update"],
                           "8 B x len x (j+2) per launch (reads V_0..V_j and w, writes w)"),
-        "k_mdot": roof("k_mdot (CGS: h = V^T w, ||w||^2)",
+        "k_mdot": roof("k_mdot", "k_mdot (CGS: h = V^T w, ||w||^2)",
                        pinfo["bytes_orth_dot"] / pinfo["n_orth_dot"],
                        pinfo["t_orth_dot_ms"] / pinfo["n_orth_dot"],
                        "8 B x len x (j+2) per launch (reads V_0..V_j and w)"),
-        "k_curlcurl": roof("k_curlcurl (stencil y = A x)", spmv_bytes, t_spmv,
+        "k_curlcurl": roof("k_curlcurl", "k_curlcurl (stencil y = A x)", spmv_bytes, t_spmv,
                            "16 B per unknown (x in, y out)"),
-        "precond_apply": roof("precond apply (passes A, B, C)", 16.0 * n_unk, t_pre,
+        "precond_apply": roof("precond_apply", "precond apply (passes A, B, C)", 16.0 * n_unk, t_pre,
                               "16 B per unknown (r in, z out); staging traffic excluded"),
     }
     share = {"k_mupdate": pinfo["t_orth_update_ms"], "k_mdot": pinfo["t_orth_dot_ms"],

@@ -85,7 +85,8 @@ typedef struct {
  * use_learned: 1 reserves room for a coarse-correction network
  *   (fmp_set_coarse_model); it is applied only once weights are set.
  * batch_boxes: boxes per pipeline batch (0 = automatic); smaller batches keep
- *   the transform staging resident in the last-level cache.
+ *   the transform staging resident in the last-level cache.  -1 = automatic,
+ *   and the workspace keeps room for every candidate of fmp_autotune.
  * use_graph: 1 = the launch sequence of an apply is captured once per
  *   (r, z) pair into a hipGraph (on a private stream, default priority) and
  *   replayed on the caller's stream; at most 64 pairs are cached, further
@@ -108,7 +109,18 @@ typedef struct {
  *   (capture_count vectors of fmp_vector_layout length, caller-owned).
  * profile: 1 = record HIP events on the solve's stream around every
  *   preconditioner apply, operator apply and (FGMRES) orthogonalisation
- *   kernel, and report the times in fmp_solve_info (adds event overhead). */
+ *   kernel, and report the times in fmp_solve_info (adds event overhead).
+ * per_domain: FGMRES only.  0 = one Krylov method on the concatenated system
+ *   of all domains, stopped on the residual of the whole vector.  1 = an
+ *   independent FGMRES per domain (own Arnoldi basis coefficients, Givens
+ *   rotations, restarts and stopping test ||b_d - A x_d|| <= rtol ||b_d - A x0_d||),
+ *   all advanced in lockstep through shared kernel launches; a domain that
+ *   has converged stops contributing.  Not combinable with the learned part
+ *   or with capture (FMP_ERR_UNSUPPORTED / FMP_ERR_INVALID_ARG).
+ * domain_iterations, domain_rel_residual: optional host arrays of n_domains
+ *   entries (may be NULL), written on return: the lockstep step at which a
+ *   domain met rtol (per_domain = 1; else the solve's step count) and each
+ *   domain's recomputed ||b_d - A x_d|| / ||b_d - A x0_d|| (0 for b_d = A x0_d). */
 typedef struct {
   int32_t solver;
   int32_t restart;
@@ -119,6 +131,9 @@ typedef struct {
   int32_t capture_count;
   double* capture;
   int32_t profile;
+  int32_t per_domain;
+  int32_t* domain_iterations;
+  double* domain_rel_residual;
 } fmp_solve_opts;
 
 typedef struct {
@@ -126,7 +141,8 @@ typedef struct {
   int32_t n_precond;           /* preconditioner applies                      */
   int32_t n_spmv;              /* operator applies                            */
   int32_t used_fallback;       /* applies where the learned part was rejected */
-  double rel_residual_true;    /* ||b - A x|| / ||b - A x0|| recomputed       */
+  double rel_residual_true;    /* ||b - A x|| / ||b - A x0|| recomputed (the
+                                  largest per-domain value when per_domain) */
   double t_total_ms;
   /* filled when opts.profile = 1 (kernel time from HIP events, ms; bytes are
    * the algorithmic HBM bytes of those launches: 8 per element read or written) */
@@ -161,13 +177,35 @@ fmp_status fmp_curlcurl_apply(fmp_handle h, const double* x, double* y, void* st
  * r, z: device, must not overlap. */
 fmp_status fmp_apply_precond(fmp_handle h, const double* r, double* z, void* stream);
 
+/* One measured candidate of fmp_autotune. */
+typedef struct {
+  int32_t batch_boxes;   /* boxes per batch (staging reused batch after batch)  */
+  int32_t streams;       /* 1: batches in order; 2: consecutive batches on two
+                            private streams with two staging buffers (overlap) */
+  double apply_ms;       /* mean preconditioner apply time (HIP events)         */
+  int32_t chosen;        /* 1 for the candidate the handle now uses             */
+} fmp_tune_entry;
+
+/* Autotuner of the preconditioner's launch plan: times fmp_apply_precond(r, z)
+ * (three applies after a warm-up, or graph replays when use_graph is set) for
+ * every candidate batch size (16 .. 1024 boxes and all boxes, per size class)
+ * and stream count, and keeps the fastest plan in the handle.  Every plan
+ * computes the same z bit for bit; only the schedule changes.  Requires a
+ * handle set up with batch_boxes = -1 (else FMP_ERR_UNSUPPORTED).  r, z:
+ * device vectors (not overlapping); z is overwritten.  entries: optional host
+ * array of max_entries records; *n_entries (may be NULL) gets the count
+ * written.  Synchronises the stream. */
+fmp_status fmp_autotune(fmp_handle h, const double* r, double* z, fmp_tune_entry* entries,
+                        int32_t max_entries, int32_t* n_entries, void* stream);
+
 /* Workspace the solver needs for `opts` (bytes).  */
 fmp_status fmp_solve_workspace(fmp_handle h, const fmp_solve_opts* opts, size_t* bytes);
 
 /* Solve A x = b.  x holds the initial guess on entry and the solution on
- * exit.  ws: device buffer of fmp_solve_workspace bytes.  Returns FMP_OK,
- * FMP_NOT_CONVERGED (x = last iterate), or FMP_ERR_BREAKDOWN (x = last finite
- * iterate).  info may be NULL. */
+ * exit; the wall slots of b and of the initial x are ignored, and those of x
+ * are 0 on exit.  ws: device buffer of fmp_solve_workspace bytes (256-byte
+ * aligned).  Returns FMP_OK, FMP_NOT_CONVERGED (x = last iterate), or
+ * FMP_ERR_BREAKDOWN (x = last finite iterate).  info may be NULL. */
 fmp_status fmp_solve(fmp_handle h, const double* b, double* x, const fmp_solve_opts* opts,
                      void* ws, size_t ws_bytes, fmp_solve_info* info, void* stream);
 

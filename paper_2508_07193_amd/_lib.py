@@ -12,7 +12,7 @@ PRECISION = {"fp64": 0, "fp32": 1, "bf16": 2}
 
 # every symbol include/flashmp.h declares
 EXPORTS = ["fmp_setup_subdomains", "fmp_vector_layout", "fmp_curlcurl_apply", "fmp_apply_precond",
-           "fmp_solve_workspace", "fmp_solve", "fmp_coarse_size", "fmp_set_coarse_model",
+           "fmp_autotune", "fmp_solve_workspace", "fmp_solve", "fmp_coarse_size", "fmp_set_coarse_model",
            "fmp_coarse_restrict", "fmp_mlp_loss_grad", "fmp_mlp_scratch_bytes", "fmp_mlp_adam",
            "fmp_destroy", "fmp_status_string", "fmp_last_error"]
 
@@ -28,10 +28,17 @@ class PrecondDesc(C.Structure):
                 ("batch_boxes", C.c_int32), ("use_graph", C.c_int32)]
 
 
+class TuneEntry(C.Structure):
+    _fields_ = [("batch_boxes", C.c_int32), ("streams", C.c_int32), ("apply_ms", C.c_double),
+                ("chosen", C.c_int32)]
+
+
 class SolveOpts(C.Structure):
     _fields_ = [("solver", C.c_int32), ("restart", C.c_int32), ("max_iter", C.c_int32),
                 ("rtol", C.c_double), ("precond", C.c_int32), ("check_every", C.c_int32),
-                ("capture_count", C.c_int32), ("capture", C.c_void_p), ("profile", C.c_int32)]
+                ("capture_count", C.c_int32), ("capture", C.c_void_p), ("profile", C.c_int32),
+                ("per_domain", C.c_int32), ("domain_iterations", C.POINTER(C.c_int32)),
+                ("domain_rel_residual", C.POINTER(C.c_double))]
 
 
 class SolveInfo(C.Structure):

@@ -106,6 +106,9 @@ class Handle:
     def new_vector(self):
         return torch.zeros(self.length, dtype=torch.float64, device=self.device)
 
+    def autotune(self, r=None, z=None, stream=None):
+        return fmp_autotune(self, r, z, stream)
+
     def curlcurl_apply(self, x, y, stream=None):
         return fmp_curlcurl_apply(self, x, y, stream)
 
@@ -130,11 +133,28 @@ def fmp_apply_precond(h, r, z, stream=None):
            "fmp_apply_precond", h.h)
 
 
+def fmp_autotune(h, r=None, z=None, stream=None):
+    """Time the candidate launch plans of the preconditioner and keep the fastest.
+
+    r defaults to a seeded N(0,1) vector; returns the measured candidates."""
+    if r is None:
+        g = torch.Generator(device="cpu").manual_seed(0)
+        r = torch.randn(h.length, generator=g, dtype=torch.float64).to(h.device)
+    if z is None:
+        z = h.new_vector()
+    ent = (_lib.TuneEntry * 64)()
+    n = C.c_int32(0)
+    _check(_lib.load().fmp_autotune(h.h, _ptr(r), _ptr(z), ent, 64, C.byref(n), _stream(stream)),
+           "fmp_autotune", h.h)
+    return [dict(batch_boxes=e.batch_boxes, streams=e.streams, apply_ms=e.apply_ms,
+                 chosen=bool(e.chosen)) for e in ent[:n.value]]
+
+
 def solve_opts(solver="fgmres", restart=30, max_iter=500, rtol=1e-8, precond=True, check_every=1,
-               capture=None, profile=False):
+               capture=None, profile=False, per_domain=False):
     o = _lib.SolveOpts({"bicgstab": 0, "fgmres": 1}[solver], int(restart), int(max_iter),
                        float(rtol), int(bool(precond)), int(check_every), 0, None,
-                       int(bool(profile)))
+                       int(bool(profile)), int(bool(per_domain)), None, None)
     if capture is not None:   # (count, length) float64 CUDA tensor receiving x_1 .. x_count
         o.capture_count = int(capture.shape[0])
         o.capture = C.c_void_p(capture.data_ptr())
@@ -151,13 +171,19 @@ def fmp_solve(h, b, x, stream=None, raise_on_breakdown=True, **kw):
         h._solve_ws = None
         h._solve_ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=h.device)
     info = _lib.SolveInfo()
+    nd = len(h.offsets) - 1
+    dom_it = (C.c_int32 * nd)()
+    dom_rel = (C.c_double * nd)()
+    o.domain_iterations = C.cast(dom_it, C.POINTER(C.c_int32))
+    o.domain_rel_residual = C.cast(dom_rel, C.POINTER(C.c_double))
     st = L.fmp_solve(h.h, _ptr(b), _ptr(x), C.byref(o), _ptr(h._solve_ws), nbytes.value,
                      C.byref(info), _stream(stream))
     ok = (0, 1) if raise_on_breakdown else (0, 1, -5)
     _check(st, "fmp_solve", h.h, ok=ok)
     out = dict(status=_lib.STATUS[st], iterations=info.iterations, n_precond=info.n_precond,
                n_spmv=info.n_spmv, used_fallback=info.used_fallback,
-               rel_residual_true=info.rel_residual_true, t_total_ms=info.t_total_ms)
+               rel_residual_true=info.rel_residual_true, t_total_ms=info.t_total_ms,
+               domain_iterations=list(dom_it), domain_rel_residual=list(dom_rel))
     if o.profile:
         out.update(t_precond_ms=info.t_precond_ms, t_spmv_ms=info.t_spmv_ms,
                    t_orth_dot_ms=info.t_orth_dot_ms, t_orth_update_ms=info.t_orth_update_ms,

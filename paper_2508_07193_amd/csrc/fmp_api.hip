@@ -36,6 +36,12 @@ constexpr int kScalH = 16;      // h column of FGMRES
 constexpr int kScalW = 64;      // ||w||^2
 constexpr int kScalY = 128;     // FGMRES update coefficients
 constexpr int kScalJ = 200;     // learned-correction judge: ||v - w||^2, ||v - w + A d||^2
+// per-group scalar block (kSD doubles per group)
+constexpr int kSD = 128;
+constexpr int kSDH = 0;         // h column and ||w||^2 before the update (<= 34)
+constexpr int kSDW = 40;        // ||w||^2 after the update
+constexpr int kSDY = 48;        // update coefficients y (<= 33)
+constexpr int kSDR = 96;        // ||r||^2 of a residual
 
 struct Parts {
   int own0, own1, box0, box1;
@@ -53,6 +59,36 @@ int class_of(int n) {
   for (int c = 0; c < kNumClasses; ++c)
     if (kClasses[c] >= n) return c;
   return -1;
+}
+
+// Cut the class-ordered boxes into batches of at most `batch` boxes of one
+// class; assign each box its staging offset inside its batch.  Returns the
+// largest batch's staging size (elements).
+long long plan_batches(fmp_ctx* h, int batch) {
+  h->launches.clear();
+  h->batch = batch;
+  long long wmax = 0;
+  const auto cls_at = [&](size_t i) {
+    const BoxDev& B = h->boxes[h->order[i]];
+    return class_of(std::max(B.nx, std::max(B.ny, B.nz)));
+  };
+  for (size_t i0 = 0; i0 < h->order.size();) {
+    const int c = cls_at(i0);
+    size_t i1 = i0;
+    while (i1 < h->order.size() && cls_at(i1) == c && (int)(i1 - i0) < batch) ++i1;
+    long long woff = 0;
+    for (size_t i = i0; i < i1; ++i) {
+      BoxDev& B = h->boxes[h->order[i]];
+      B.w_off = woff;                 // staging is reused batch after batch
+      woff += 3 * B.vol;
+    }
+    wmax = std::max(wmax, woff);
+    if (c >= 0)
+      h->launches.push_back(Launch{c, h->wa0[i0], h->wa0[i1] - h->wa0[i0], h->wb0[i0],
+                                   h->wb0[i1] - h->wb0[i0]});
+    i0 = i1;
+  }
+  return wmax;
 }
 
 // Orthonormal DCT-II (rows p, columns l) and DST-I embedded in an n x n
@@ -148,7 +184,7 @@ static fmp_status precond_launches(fmp_ctx* h, const double* r, double* z, hipSt
   // Two or more batches: batch k runs on private stream k % 2 with staging
   // buffer k % 2, so the gather pass of one batch overlaps the solve passes
   // of the previous one.  Batches write disjoint parts of z.
-  const bool two = h->launches.size() > 1 && h->d_Wb;
+  const bool two = h->launches.size() > 1 && h->d_Wb && h->nstreams == 2;
   hipStream_t bs[2] = {s, s};
   if (two) {
     for (int i = 0; i < 2; ++i)
@@ -313,6 +349,44 @@ fmp_status fmp_setup_subdomains(const fmp_domain_desc* domains, int32_t n_domain
   }
   h->offsets.push_back(off);
   h->len = off;
+  if (n_domains > kRedBlocks) {
+    h->err = "more domains than reduction blocks (1024)";
+    return FMP_ERR_UNSUPPORTED;
+  }
+  for (int d = 0; d < n_domains; ++d)
+    if (h->offsets[d + 1] - h->offsets[d] >= (1LL << 31)) return FMP_ERR_UNSUPPORTED;
+
+  // ---- reduction segments: blocks dealt to domains in proportion to size,
+  // at least one each, kRedBlocks in total
+  std::vector<SegDev> map_glob(kRedBlocks), segs_dom(n_domains), map_dom(kRedBlocks);
+  {
+    const SegDev g{0, h->len, 0, kRedBlocks, 0, 0};
+    std::fill(map_glob.begin(), map_glob.end(), g);
+    std::vector<int> nb(n_domains);
+    int tot = 0;
+    for (int d = 0; d < n_domains; ++d) {
+      const long long ld = h->offsets[d + 1] - h->offsets[d];
+      h->seg_len.push_back(ld);
+      nb[d] = std::max(1, (int)((double)kRedBlocks * (double)ld / (double)h->len));
+      tot += nb[d];
+    }
+    while (tot > kRedBlocks) {   // take from the domain with the most blocks
+      int k = (int)(std::max_element(nb.begin(), nb.end()) - nb.begin());
+      --nb[k]; --tot;
+    }
+    while (tot < kRedBlocks) {   // give to the domain with the most elements per block
+      int k = 0;
+      for (int d = 1; d < n_domains; ++d)
+        if ((double)h->seg_len[d] / nb[d] > (double)h->seg_len[k] / nb[k]) k = d;
+      ++nb[k]; ++tot;
+    }
+    int b0 = 0;
+    for (int d = 0; d < n_domains; ++d) {
+      segs_dom[d] = SegDev{h->offsets[d], h->offsets[d + 1], b0, nb[d], d, d};
+      for (int b = b0; b < b0 + nb[d]; ++b) map_dom[b] = segs_dom[d];
+      b0 += nb[d];
+    }
+  }
 
   // ---- transform tables for each side in use
   std::vector<int> side_slot(kMaxSide + 1, -1);
@@ -386,40 +460,36 @@ fmp_status fmp_setup_subdomains(const fmp_domain_desc* domains, int32_t n_domain
     }
   }
 
-  // ---- size classes and batches
-  int batch = pd->batch_boxes;
-  if (batch <= 0) batch = (h->prec == FMP_FP64) ? 128 : 256;
-  std::vector<int> order(h->boxes.size());
-  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+  // ---- size classes, work lists and batches
   std::vector<int> cls(h->boxes.size());
   for (size_t i = 0; i < h->boxes.size(); ++i) {
     const BoxDev& B = h->boxes[i];
     cls[i] = class_of(std::max(B.nx, std::max(B.ny, B.nz)));
   }
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cls[a] < cls[b]; });
+  h->order.resize(h->boxes.size());
+  for (size_t i = 0; i < h->order.size(); ++i) h->order[i] = (int)i;
+  std::stable_sort(h->order.begin(), h->order.end(), [&](int a, int b) { return cls[a] < cls[b]; });
   std::vector<int4> work_a, work_b;
-  long long w_batch_max = 0;
-  for (size_t i0 = 0; i0 < order.size();) {
-    const int c = cls[order[i0]];
-    size_t i1 = i0;
-    while (i1 < order.size() && cls[order[i1]] == c && (int)(i1 - i0) < batch) ++i1;
-    Launch L{c, (int)work_a.size(), 0, (int)work_b.size(), 0};
-    const int zs = (h->prec == FMP_BF16) ? mfma_zslab(c) : pass_a_zslab(c);
-    long long woff = 0;
-    for (size_t i = i0; i < i1; ++i) {
-      BoxDev& B = h->boxes[order[i]];
-      B.w_off = woff;                 // staging is reused batch after batch
-      woff += 3 * B.vol;
-      for (int q = 0; q < 3; ++q)
-        for (int z0 = 0; z0 < B.nz; z0 += zs) work_a.push_back(make_int4(order[i], q, z0, 0));
-      for (int c0 = 0; c0 < B.nx * B.ny; c0 += 64) work_b.push_back(make_int4(order[i], c0, 0, 0));
-    }
-    w_batch_max = std::max(w_batch_max, woff);
-    L.na = (int)work_a.size() - L.a0;
-    L.nb = (int)work_b.size() - L.b0;
-    h->launches.push_back(L);
-    i0 = i1;
+  for (size_t i = 0; i < h->order.size(); ++i) {
+    const int bi = h->order[i];
+    const BoxDev& B = h->boxes[bi];
+    h->wa0.push_back((int)work_a.size());
+    h->wb0.push_back((int)work_b.size());
+    if (cls[bi] < 0) continue;
+    const int zs = (h->prec == FMP_BF16) ? mfma_zslab(cls[bi]) : pass_a_zslab(cls[bi]);
+    for (int q = 0; q < 3; ++q)
+      for (int z0 = 0; z0 < B.nz; z0 += zs) work_a.push_back(make_int4(bi, q, z0, 0));
+    for (int c0 = 0; c0 < B.nx * B.ny; c0 += 64) work_b.push_back(make_int4(bi, c0, 0, 0));
   }
+  h->wa0.push_back((int)work_a.size());
+  h->wb0.push_back((int)work_b.size());
+  // batch = -1: keep room for every candidate of fmp_autotune (whole classes)
+  h->tunable = pd->batch_boxes < 0;
+  int batch = pd->batch_boxes;
+  if (batch <= 0) batch = (h->prec == FMP_FP64) ? 128 : 256;
+  h->w_cap = plan_batches(h.get(), h->tunable ? (int)h->boxes.size() : batch);
+  if (h->tunable) plan_batches(h.get(), batch);
+  const long long w_batch_max = h->w_cap;
 
   // ---- stencil tiles
   std::vector<StencilTile> tiles;
@@ -446,10 +516,13 @@ fmp_status fmp_setup_subdomains(const fmp_domain_desc* domains, int32_t n_domain
   const size_t o_wb = cur; cur = align_up(cur + work_b.size() * sizeof(int4));
   const size_t o_part = cur; cur = align_up(cur + (size_t)kMaxDots * kRedBlocks * 8);
   const size_t o_S = cur; cur = align_up(cur + kScal * 8);
+  const size_t o_map = cur; cur = align_up(cur + (2 * (size_t)kRedBlocks + 1 + n_domains) * sizeof(SegDev));
+  const size_t sd_bytes = (size_t)n_domains * (kSD + 1) * 8 + (size_t)n_domains * 4;
+  const size_t o_SD = cur; cur = align_up(cur + sd_bytes);
   const size_t o_learn = cur;
   if (h->use_learned) cur = align_up(cur + fmp_coarse_workspace(h->nsub, 512));
   const size_t o_W = cur; cur = align_up(cur + (size_t)w_batch_max * wsz);
-  const bool two_w = h->launches.size() > 1;
+  const bool two_w = h->launches.size() > 1 || h->tunable;
   const size_t o_W2 = cur;
   if (two_w) cur = align_up(cur + (size_t)w_batch_max * wsz);
   const size_t need = cur;
@@ -472,6 +545,13 @@ fmp_status fmp_setup_subdomains(const fmp_domain_desc* domains, int32_t n_domain
   h->d_work_b = (int4*)(base + o_wb);
   h->d_part = (double*)(base + o_part);
   h->d_S = (double*)(base + o_S);
+  h->d_map_glob = (SegDev*)(base + o_map);
+  h->d_map_dom = h->d_map_glob + kRedBlocks;
+  h->d_segs_glob = h->d_map_dom + kRedBlocks;
+  h->d_segs_dom = h->d_segs_glob + 1;
+  h->d_SD = (double*)(base + o_SD);
+  h->d_fac = h->d_SD + (size_t)n_domains * kSD;
+  h->d_act = (int*)(h->d_fac + n_domains);
   h->d_W = base + o_W;
   if (two_w) h->d_Wb = base + o_W2;
   if (h->use_learned) fmp_coarse_bind(h.get(), base + o_learn);
@@ -503,7 +583,18 @@ fmp_status fmp_setup_subdomains(const fmp_domain_desc* domains, int32_t n_domain
                             hipMemcpyHostToDevice, s));
   HIPCHK(hp, hipMemcpyAsync(h->d_work_b, work_b.data(), work_b.size() * sizeof(int4),
                             hipMemcpyHostToDevice, s));
+  HIPCHK(hp, hipMemcpyAsync(h->d_map_glob, map_glob.data(), kRedBlocks * sizeof(SegDev),
+                            hipMemcpyHostToDevice, s));
+  HIPCHK(hp, hipMemcpyAsync(h->d_map_dom, map_dom.data(), kRedBlocks * sizeof(SegDev),
+                            hipMemcpyHostToDevice, s));
+  HIPCHK(hp, hipMemcpyAsync(h->d_segs_glob, map_glob.data(), sizeof(SegDev),
+                            hipMemcpyHostToDevice, s));
+  HIPCHK(hp, hipMemcpyAsync(h->d_segs_dom, segs_dom.data(), n_domains * sizeof(SegDev),
+                            hipMemcpyHostToDevice, s));
   HIPCHK(hp, hipHostMalloc((void**)&h->h_S, kScal * 8, hipHostMallocDefault));
+  HIPCHK(hp, hipHostMalloc((void**)&h->h_SD, sd_bytes, hipHostMallocDefault));
+  h->h_fac = h->h_SD + (size_t)n_domains * kSD;
+  h->h_act = (int*)(h->h_fac + n_domains);
   HIPCHK(hp, hipStreamSynchronize(s));   // host staging vectors go out of scope
   *out = h.release();
   return FMP_OK;
@@ -518,6 +609,7 @@ fmp_status fmp_vector_layout(fmp_handle h, int64_t* offsets) {
 fmp_status fmp_destroy(fmp_handle h) {
   if (!h) return FMP_ERR_INVALID_ARG;
   if (h->h_S) (void)hipHostFree(h->h_S);
+  if (h->h_SD) (void)hipHostFree(h->h_SD);
   for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.exec);
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   for (int i = 0; i < 2; ++i) {
@@ -549,6 +641,71 @@ fmp_status fmp_apply_precond(fmp_handle h, const double* r, double* z, void* str
     if (st != FMP_OK) return st;
   }
   return precond_apply(h, r, z, s, coarse);
+}
+
+fmp_status fmp_autotune(fmp_handle h, const double* r, double* z, fmp_tune_entry* entries,
+                        int32_t max_entries, int32_t* n_entries, void* stream) {
+  if (!h || !r || !z || max_entries < 0) return FMP_ERR_INVALID_ARG;
+  if (overlaps(r, z, h->len * 8)) return FMP_ERR_ALIAS;
+  if (!h->precond_ok) return FMP_ERR_UNSUPPORTED;
+  if (!h->tunable) {
+    h->err = "fmp_autotune needs a handle set up with batch_boxes = -1";
+    return FMP_ERR_UNSUPPORTED;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const int nbox = (int)h->boxes.size();
+  std::vector<int> batches;
+  for (int b : {16, 32, 64, 128, 256, 512, 1024})
+    if (b < nbox) batches.push_back(b);
+  batches.push_back(nbox);
+  struct Cand { int batch, ns; double ms; };
+  std::vector<Cand> cands;
+  for (int b : batches)
+    for (int ns = 1; ns <= 2; ++ns) cands.push_back({b, ns, 0.0});
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(h, hipEventCreate(&e0));
+  HIPCHK(h, hipEventCreate(&e1));
+  const double* coarse = nullptr;   // the learned part does not depend on the plan
+  auto use = [&](int b, int ns) -> fmp_status {
+    for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.exec);
+    h->graphs.clear();
+    plan_batches(h, b);
+    h->nstreams = ns;
+    HIPCHK(h, hipMemcpyAsync(h->d_boxes, h->boxes.data(), h->boxes.size() * sizeof(BoxDev),
+                             hipMemcpyHostToDevice, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    return FMP_OK;
+  };
+  fmp_status st = FMP_OK;
+  for (Cand& c : cands) {
+    if ((st = use(c.batch, c.ns)) != FMP_OK) break;
+    if (c.ns == 2 && h->launches.size() < 2) { c.ms = -1.0; continue; }   // same as 1 stream
+    if ((st = precond_apply(h, r, z, s, coarse)) != FMP_OK) break;      // capture / warm up
+    HIPCHK(h, hipEventRecord(e0, s));
+    constexpr int kReps = 3;
+    for (int k = 0; k < kReps && st == FMP_OK; ++k) st = precond_apply(h, r, z, s, coarse);
+    if (st != FMP_OK) break;
+    HIPCHK(h, hipEventRecord(e1, s));
+    HIPCHK(h, hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(h, hipEventElapsedTime(&ms, e0, e1));
+    c.ms = ms / kReps;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != FMP_OK) return st;
+  const Cand* best = nullptr;
+  for (const Cand& c : cands)
+    if (c.ms >= 0.0 && (!best || c.ms < best->ms)) best = &c;
+  if ((st = use(best->batch, best->ns)) != FMP_OK) return st;
+  int k = 0;
+  for (const Cand& c : cands) {
+    if (c.ms < 0.0) continue;
+    if (entries && k < max_entries) entries[k] = fmp_tune_entry{c.batch, c.ns, c.ms, &c == best};
+    ++k;
+  }
+  if (n_entries) *n_entries = std::min(k, max_entries);
+  return FMP_OK;
 }
 
 fmp_status fmp_solve_workspace(fmp_handle h, const fmp_solve_opts* o, size_t* bytes) {
@@ -659,37 +816,67 @@ fmp_status A(Ctx& c, const double* x, double* y) {
   return st;
 }
 
-// profiled CGS kernels: h = V^T w (+ ||w||^2), then w -= V h (+ ||w||^2)
-hipError_t orth_dot(Ctx& c, const double* V, long long ldv, int nv, const double* w) {
+// Reduction groups of a solve: the whole system (one group), or one group
+// per domain (independent solves advanced in lockstep).
+struct Groups {
+  int n;
+  const SegDev* map;    // per block
+  const SegDev* segs;   // per group
+};
+
+// profiled CGS kernels: h = V^T w (+ ||w||^2), then w -= V h (+ ||w||^2);
+// act_len = elements of the groups taking part (for the byte count)
+hipError_t orth_dot(Ctx& c, const Groups& G, const int* act, double act_len, const double* V,
+                    long long ldv, int nv, const double* w) {
   hipEvent_t e = c.begin();
-  const hipError_t r = launch_mdot(V, ldv, nv, w, c.h->len, c.h->d_part, c.s);
+  const hipError_t r = launch_mdot(V, ldv, nv, w, G.map, act, c.h->d_part, c.s);
   c.end(Prof::DOT, e);
   c.info->n_orth_dot++;
-  c.info->bytes_orth_dot += 8.0 * (double)c.h->len * (nv + 1);
+  c.info->bytes_orth_dot += 8.0 * act_len * (nv + 1);
   return r;
 }
-hipError_t orth_update(Ctx& c, const double* V, long long ldv, int nv, const double* hcoef,
-                       double* w) {
+hipError_t orth_update(Ctx& c, const Groups& G, const int* act, double act_len, const double* V,
+                       long long ldv, int nv, const double* hcoef, int hld, double* w) {
   hipEvent_t e = c.begin();
-  const hipError_t r = launch_mupdate(V, ldv, nv, hcoef, w, c.h->len, c.h->d_part, c.s);
+  const hipError_t r =
+      launch_mupdate(V, ldv, nv, hcoef, hld, w, G.map, act, c.h->d_part, c.s);
   c.end(Prof::UPD, e);
   c.info->n_orth_update++;
-  c.info->bytes_orth_update += 8.0 * (double)c.h->len * (nv + 2);
+  c.info->bytes_orth_update += 8.0 * act_len * (nv + 2);
   return r;
 }
 
-// r = b - A x into r (tmp used for A x), returns ||r||^2 through the host mirror
+// r = b - A x with wall slots 0 (tmp holds A x); ||r_d||^2 per domain into
+// rr[0..ndom) (host), summed in domain order into *total.
 fmp_status residual(Ctx& c, const double* b, const double* x, double* r, double* tmp,
-                    double* rr) {
+                    std::vector<double>& rr, double* total) {
   fmp_status st = A(c, x, tmp);
   if (st) return st;
   fmp_ctx* h = c.h;
-  HIPCHK(h, launch_sub_norm(b, tmp, r, h->len, h->d_part, c.s));
-  HIPCHK(h, launch_reduce(h->d_part, 1, h->d_S + 7, 0, h->d_S, c.s));
-  HIPCHK(h, hipMemcpyAsync(h->h_S + 7, h->d_S + 7, 8, hipMemcpyDeviceToHost, c.s));
+  const int nd = (int)h->doms.size();
+  HIPCHK(h, launch_sub_norm(b, tmp, r, h->d_map_dom, h->d_doms, h->d_part, c.s));
+  HIPCHK(h, launch_reduce_seg(h->d_part, 1, h->d_segs_dom, nd, h->d_SD + kSDR, kSD, c.s));
+  HIPCHK(h, hipMemcpyAsync(h->h_SD, h->d_SD, (size_t)nd * kSD * 8, hipMemcpyDeviceToHost, c.s));
   HIPCHK(h, hipStreamSynchronize(c.s));
-  *rr = h->h_S[7];
+  rr.assign(nd, 0.0);
+  double t = 0.0;
+  for (int d = 0; d < nd; ++d) {
+    rr[d] = h->h_SD[(size_t)d * kSD + kSDR];
+    t += rr[d];
+  }
+  *total = t;
   return FMP_OK;
+}
+
+// per-domain outputs of a solve
+void report_domains(Ctx& c, const std::vector<double>& rr0, const std::vector<double>& rr,
+                    const std::vector<int>& iters) {
+  const int nd = (int)rr.size();
+  for (int d = 0; d < nd; ++d) {
+    if (c.o->domain_rel_residual)
+      c.o->domain_rel_residual[d] = rr0[d] > 0.0 ? sqrt(rr[d] / rr0[d]) : 0.0;
+    if (c.o->domain_iterations) c.o->domain_iterations[d] = iters[d];
+  }
 }
 
 fmp_status bicgstab(Ctx& c, const double* b, double* x, double* ws) {
@@ -701,12 +888,18 @@ fmp_status bicgstab(Ctx& c, const double* b, double* x, double* ws) {
   const double tol = c.o->rtol;
   const int check = std::max(1, c.o->check_every);
   double rr;
-  fmp_status st = residual(c, b, x, r, t, &rr);
+  std::vector<double> rrd0, rrd;
+  HIPCHK(h, launch_zero_walls(x, h->d_doms, (int)h->doms.size(), c.s));
+  fmp_status st = residual(c, b, x, r, t, rrd0, &rr);
   if (st) return st;
   if (!isfinite(rr)) return FMP_ERR_BREAKDOWN;
   const double r0 = sqrt(rr);
   c.info->rel_residual_true = 0.0;
-  if (r0 == 0.0) return FMP_OK;
+  rrd = rrd0;
+  auto report = [&](int iters) {
+    report_domains(c, rrd0, rrd, std::vector<int>(rrd0.size(), iters));
+  };
+  if (r0 == 0.0) { report(0); return FMP_OK; }
   int it = 0;
   bool broke = false;
   while (it < c.o->max_iter) {
@@ -744,15 +937,67 @@ fmp_status bicgstab(Ctx& c, const double* b, double* x, double* ws) {
         if (hs[3] == 0.0 || hs[0] == 0.0) { broke = true; break; }
       }
     }
-    if ((st = residual(c, b, x, r, t, &rr))) return st;
+    if ((st = residual(c, b, x, r, t, rrd, &rr))) return st;
     c.info->rel_residual_true = sqrt(rr) / r0;
     if (!isfinite(rr)) broke = true;
-    if (!broke && sqrt(rr) <= tol * r0) { c.info->iterations = it; return FMP_OK; }
+    if (!broke && sqrt(rr) <= tol * r0) {
+      c.info->iterations = it;
+      report(it);
+      return FMP_OK;
+    }
     if (broke || !restart) break;
   }
   c.info->iterations = it;
+  report(it);
   return broke ? FMP_ERR_BREAKDOWN : FMP_NOT_CONVERGED;
 }
+
+// Arnoldi state of one group's FGMRES cycle.
+struct Arnoldi {
+  int m = 0;
+  std::vector<double> H, cs, sn, g, y;
+  double r0 = 0.0, beta = 0.0;
+  int ncols = 0;
+  bool active = false;     // iterating in the current cycle
+  bool finished = false;   // recomputed residual met the tolerance
+  int iters = 0;           // Arnoldi steps this group has taken
+  void start(int m_, double beta_) {
+    m = m_;
+    H.assign((size_t)(m + 1) * m, 0.0);
+    cs.assign(m, 0.0); sn.assign(m, 0.0); y.assign(m, 0.0);
+    g.assign(m + 1, 0.0);
+    g[0] = beta_;
+    ncols = 0;
+  }
+  // append column j (h_0..h_j, h_{j+1} = hn), rotate it, return |g_{j+1}|
+  double add(int j, const double* hcol, double hn) {
+    for (int i = 0; i <= j; ++i) H[i * m + j] = hcol[i];
+    H[(j + 1) * m + j] = hn;
+    for (int i = 0; i < j; ++i) {
+      const double a = H[i * m + j], bb = H[(i + 1) * m + j];
+      H[i * m + j] = cs[i] * a + sn[i] * bb;
+      H[(i + 1) * m + j] = -sn[i] * a + cs[i] * bb;
+    }
+    const double a = H[j * m + j], bb = H[(j + 1) * m + j];
+    const double den = hypot(a, bb);
+    cs[j] = den == 0.0 ? 1.0 : a / den;
+    sn[j] = den == 0.0 ? 0.0 : bb / den;
+    H[j * m + j] = cs[j] * a + sn[j] * bb;
+    H[(j + 1) * m + j] = 0.0;
+    g[j + 1] = -sn[j] * g[j];
+    g[j] = cs[j] * g[j];
+    ncols = j + 1;
+    return fabs(g[j + 1]);
+  }
+  // back substitution of the triangular least-squares system
+  void solve() {
+    for (int i = ncols - 1; i >= 0; --i) {
+      double acc = g[i];
+      for (int k = i + 1; k < ncols; ++k) acc -= H[i * m + k] * y[k];
+      y[i] = acc / H[i * m + i];
+    }
+  }
+};
 
 fmp_status fgmres(Ctx& c, const double* b, double* x, double* ws) {
   fmp_ctx* h = c.h;
@@ -762,28 +1007,81 @@ fmp_status fgmres(Ctx& c, const double* b, double* x, double* ws) {
   double* V = ws;
   double* Z = ws + (size_t)(m + 1) * vb;
   const double tol = c.o->rtol;
+  const int nd = (int)h->doms.size();
+  const bool per = c.o->per_domain && nd > 1;
+  const Groups G = per ? Groups{nd, h->d_map_dom, h->d_segs_dom}
+                       : Groups{1, h->d_map_glob, h->d_segs_glob};
+  const int ng = G.n;
   double* hs = h->h_S;
-  double beta2;
-  fmp_status st = residual(c, b, x, V, Z, &beta2);
+  double* SD = h->h_SD;
+  std::vector<Arnoldi> grp(ng);
+  std::vector<double> glen(ng, 0.0);
+  for (int d = 0; d < nd; ++d) glen[per ? d : 0] += (double)h->seg_len[d];
+
+  HIPCHK(h, launch_zero_walls(x, h->d_doms, nd, c.s));
+  std::vector<double> rrd0, rrd;
+  double tot;
+  fmp_status st = residual(c, b, x, V, Z, rrd0, &tot);
   if (st) return st;
-  if (!isfinite(beta2)) return FMP_ERR_BREAKDOWN;
-  double beta = sqrt(beta2);
-  const double r0 = beta;
-  c.info->rel_residual_true = 0.0;
-  if (r0 == 0.0) return FMP_OK;
+  rrd = rrd0;
+  std::vector<int> dom_it(nd, 0);
+  auto group_rr = [&](const std::vector<double>& rr, int g) {
+    if (per) return rr[g];
+    double t = 0.0;
+    for (double v : rr) t += v;
+    return t;
+  };
+  auto finish = [&](int it, fmp_status code) {
+    c.info->iterations = it;
+    double worst = 0.0;
+    for (int g = 0; g < ng; ++g)
+      worst = std::max(worst, grp[g].r0 > 0.0 ? grp[g].beta / grp[g].r0 : 0.0);
+    c.info->rel_residual_true = worst;
+    for (int d = 0; d < nd; ++d) dom_it[d] = per ? grp[d].iters : it;
+    report_domains(c, rrd0, rrd, dom_it);
+    return code;
+  };
+  bool all_done = true;
+  for (int g = 0; g < ng; ++g) {
+    const double r2 = group_rr(rrd0, g);
+    if (!isfinite(r2)) return FMP_ERR_BREAKDOWN;
+    grp[g].r0 = grp[g].beta = sqrt(r2);
+    grp[g].finished = grp[g].r0 == 0.0;
+    all_done = all_done && grp[g].finished;
+  }
+  if (all_done) return finish(0, FMP_OK);
+
+  auto active_len = [&]() {
+    double t = 0.0;
+    for (int g = 0; g < ng; ++g)
+      if (grp[g].active) t += glen[g];
+    return t;
+  };
+  // group scale factors and activity flags to the device
+  int* act = h->h_act;
+  auto push = [&]() -> hipError_t {
+    hipError_t e = hipMemcpyAsync(h->d_fac, h->h_fac, (size_t)ng * 8, hipMemcpyHostToDevice, c.s);
+    if (e != hipSuccess) return e;
+    return hipMemcpyAsync(h->d_act, act, (size_t)ng * 4, hipMemcpyHostToDevice, c.s);
+  };
+
   int it = 0;
-  std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
   while (it < c.o->max_iter) {
-    HIPCHK(h, launch_scale_copy(V, 1.0 / beta, V, n, c.s));
-    std::fill(H.begin(), H.end(), 0.0);
-    std::fill(g.begin(), g.end(), 0.0);
-    g[0] = beta;
-    int ncols = 0;
+    // new cycle: v_0 = r / beta per group (0 for finished groups)
+    for (int g = 0; g < ng; ++g) {
+      Arnoldi& A_ = grp[g];
+      A_.active = !A_.finished;
+      A_.start(m, A_.beta);
+      h->h_fac[g] = A_.active ? 1.0 / A_.beta : 0.0;
+      act[g] = A_.active ? 1 : 0;
+    }
+    HIPCHK(h, push());
+    HIPCHK(h, launch_scale_seg(V, h->d_fac, V, G.map, c.s));
     for (int j = 0; j < m; ++j) {
       double* vj = V + (size_t)j * vb;
       double* zj = Z + (size_t)j * vb;
       double* w = V + (size_t)(j + 1) * vb;
-      const bool learned = c.o->precond != 0 && h->learned_set;
+      const bool learned = !per && c.o->precond != 0 && h->learned_set;
       if ((st = M(c, vj, zj, learned))) return st;
       if ((st = A(c, zj, w))) return st;
       if (learned) {
@@ -800,79 +1098,101 @@ fmp_status fgmres(Ctx& c, const double* b, double* x, double* ws) {
           if ((st = A(c, zj, w))) return st;
         }
       }
-      // classical Gram-Schmidt: h = V^T w (and ||w||^2), w -= V h, ||w||^2
-      HIPCHK(h, orth_dot(c, V, (long long)vb, j + 1, w));
-      HIPCHK(h, launch_reduce(h->d_part, j + 2, h->d_S + kScalH, 0, h->d_S, c.s));
-      HIPCHK(h, orth_update(c, V, (long long)vb, j + 1, h->d_S + kScalH, w));
-      HIPCHK(h, launch_reduce(h->d_part, 1, h->d_S + kScalW, 0, h->d_S, c.s));
-      HIPCHK(h, hipMemcpyAsync(hs, h->d_S, kScal * 8, hipMemcpyDeviceToHost, c.s));
+      // classical Gram-Schmidt per group: h = V^T w (and ||w||^2), w -= V h, ||w||^2
+      const double alen = active_len();
+      HIPCHK(h, orth_dot(c, G, h->d_act, alen, V, (long long)vb, j + 1, w));
+      HIPCHK(h, launch_reduce_seg(h->d_part, j + 2, G.segs, ng, h->d_SD + kSDH, kSD, c.s));
+      HIPCHK(h, orth_update(c, G, h->d_act, alen, V, (long long)vb, j + 1, h->d_SD + kSDH, kSD, w));
+      HIPCHK(h, launch_reduce_seg(h->d_part, 1, G.segs, ng, h->d_SD + kSDW, kSD, c.s));
+      HIPCHK(h, hipMemcpyAsync(SD, h->d_SD, (size_t)ng * kSD * 8, hipMemcpyDeviceToHost, c.s));
       HIPCHK(h, hipStreamSynchronize(c.s));
       c.harvest();
-      std::vector<double> hcol(hs + kScalH, hs + kScalH + j + 1);
-      const double wn0 = sqrt(hs[kScalH + j + 1]);
-      double hn = sqrt(hs[kScalW]);
-      if (hn < 0.1 * wn0) {   // second CGS pass
-        HIPCHK(h, orth_dot(c, V, (long long)vb, j + 1, w));
-        HIPCHK(h, launch_reduce(h->d_part, j + 2, h->d_S + kScalH, 0, h->d_S, c.s));
-        HIPCHK(h, orth_update(c, V, (long long)vb, j + 1, h->d_S + kScalH, w));
-        HIPCHK(h, launch_reduce(h->d_part, 1, h->d_S + kScalW, 0, h->d_S, c.s));
-        HIPCHK(h, hipMemcpyAsync(hs, h->d_S, kScal * 8, hipMemcpyDeviceToHost, c.s));
+      std::vector<double> hcol((size_t)ng * (j + 1)), hn(ng, 0.0);
+      bool reorth = false;
+      for (int g = 0; g < ng; ++g) {
+        act[g] = 0;
+        if (!grp[g].active) continue;
+        const double* sg = SD + (size_t)g * kSD;
+        for (int i = 0; i <= j; ++i) hcol[(size_t)g * (j + 1) + i] = sg[kSDH + i];
+        const double wn0 = sqrt(sg[kSDH + j + 1]);
+        hn[g] = sqrt(sg[kSDW]);
+        if (hn[g] < 0.1 * wn0) { act[g] = 1; reorth = true; }   // second CGS pass
+      }
+      if (reorth) {
+        double rlen = 0.0;
+        for (int g = 0; g < ng; ++g)
+          if (act[g]) rlen += glen[g];
+        HIPCHK(h, hipMemcpyAsync(h->d_act, act, (size_t)ng * 4, hipMemcpyHostToDevice, c.s));
+        HIPCHK(h, orth_dot(c, G, h->d_act, rlen, V, (long long)vb, j + 1, w));
+        HIPCHK(h, launch_reduce_seg(h->d_part, j + 2, G.segs, ng, h->d_SD + kSDH, kSD, c.s));
+        HIPCHK(h, orth_update(c, G, h->d_act, rlen, V, (long long)vb, j + 1, h->d_SD + kSDH, kSD, w));
+        HIPCHK(h, launch_reduce_seg(h->d_part, 1, G.segs, ng, h->d_SD + kSDW, kSD, c.s));
+        HIPCHK(h, hipMemcpyAsync(SD, h->d_SD, (size_t)ng * kSD * 8, hipMemcpyDeviceToHost, c.s));
         HIPCHK(h, hipStreamSynchronize(c.s));
         c.harvest();
-        for (int i = 0; i <= j; ++i) hcol[i] += hs[kScalH + i];
-        hn = sqrt(hs[kScalW]);
-      }
-      if (!isfinite(hn)) return FMP_ERR_BREAKDOWN;
-      for (int i = 0; i <= j; ++i) H[i * m + j] = hcol[i];
-      H[(j + 1) * m + j] = hn;
-      for (int i = 0; i < j; ++i) {
-        const double a = H[i * m + j], bb = H[(i + 1) * m + j];
-        H[i * m + j] = cs[i] * a + sn[i] * bb;
-        H[(i + 1) * m + j] = -sn[i] * a + cs[i] * bb;
-      }
-      const double a = H[j * m + j], bb = H[(j + 1) * m + j];
-      const double den = hypot(a, bb);
-      cs[j] = den == 0.0 ? 1.0 : a / den;
-      sn[j] = den == 0.0 ? 0.0 : bb / den;
-      H[j * m + j] = cs[j] * a + sn[j] * bb;
-      H[(j + 1) * m + j] = 0.0;
-      g[j + 1] = -sn[j] * g[j];
-      g[j] = cs[j] * g[j];
-      ++it;
-      ncols = j + 1;
-      if (c.o->capture && it <= c.o->capture_count) {   // x_it = x + Z y for the current LS solution
-        for (int i = ncols - 1; i >= 0; --i) {
-          double acc = g[i];
-          for (int k = i + 1; k < ncols; ++k) acc -= H[i * m + k] * y[k];
-          y[i] = acc / H[i * m + i];
+        for (int g = 0; g < ng; ++g) {
+          if (!act[g]) continue;
+          const double* sg = SD + (size_t)g * kSD;
+          for (int i = 0; i <= j; ++i) hcol[(size_t)g * (j + 1) + i] += sg[kSDH + i];
+          hn[g] = sqrt(sg[kSDW]);
         }
-        for (int i = 0; i < ncols; ++i) hs[kScalY + i] = y[i];
+      }
+      ++it;
+      bool any = false;
+      for (int g = 0; g < ng; ++g) {
+        Arnoldi& A_ = grp[g];
+        if (!A_.active) { h->h_fac[g] = 0.0; act[g] = 0; continue; }
+        if (!isfinite(hn[g])) return FMP_ERR_BREAKDOWN;
+        const double est = A_.add(j, &hcol[(size_t)g * (j + 1)], hn[g]);
+        A_.iters++;
+        if (hn[g] == 0.0 || est <= tol * A_.r0) A_.active = false;
+        any = any || A_.active;
+        h->h_fac[g] = A_.active ? 1.0 / hn[g] : 0.0;
+        act[g] = A_.active ? 1 : 0;
+      }
+      if (c.o->capture && it <= c.o->capture_count) {   // x_it = x + Z y (one group)
+        Arnoldi& A0 = grp[0];
+        A0.solve();
+        for (int i = 0; i < A0.ncols; ++i) SD[kSDY + i] = A0.y[i];
         double* slot = c.o->capture + (size_t)(it - 1) * n;
-        HIPCHK(h, hipMemcpyAsync(h->d_S + kScalY, hs + kScalY, ncols * 8, hipMemcpyHostToDevice, c.s));
+        HIPCHK(h, hipMemcpyAsync(h->d_SD + kSDY, SD + kSDY, A0.ncols * 8, hipMemcpyHostToDevice, c.s));
         HIPCHK(h, hipMemcpyAsync(slot, x, n * 8, hipMemcpyDeviceToDevice, c.s));
-        HIPCHK(h, launch_xupdate(Z, (long long)vb, ncols, h->d_S + kScalY, slot, n, c.s));
+        HIPCHK(h, launch_xupdate(Z, (long long)vb, A0.ncols, h->d_SD + kSDY, kSD, slot, G.map, c.s));
         HIPCHK(h, hipStreamSynchronize(c.s));
       }
-      if (hn == 0.0 || fabs(g[j + 1]) <= tol * r0 || it >= c.o->max_iter) break;
-      HIPCHK(h, launch_scale_copy(w, 1.0 / hn, w, n, c.s));
+      if (!any || it >= c.o->max_iter) break;
+      HIPCHK(h, push());
+      HIPCHK(h, launch_scale_seg(w, h->d_fac, w, G.map, c.s));
     }
-    // back substitution of the triangular least-squares system
-    for (int i = ncols - 1; i >= 0; --i) {
-      double acc = g[i];
-      for (int k = i + 1; k < ncols; ++k) acc -= H[i * m + k] * y[k];
-      y[i] = acc / H[i * m + i];
+    // x += Z y per group (y = 0 beyond a group's own column count)
+    int ncmax = 0;
+    for (int g = 0; g < ng; ++g) {
+      Arnoldi& A_ = grp[g];
+      double* sy = SD + (size_t)g * kSD + kSDY;
+      for (int i = 0; i < m; ++i) sy[i] = 0.0;
+      if (A_.finished || A_.ncols == 0) continue;
+      A_.solve();
+      for (int i = 0; i < A_.ncols; ++i) sy[i] = A_.y[i];
+      ncmax = std::max(ncmax, A_.ncols);
     }
-    for (int i = 0; i < ncols; ++i) hs[kScalY + i] = y[i];
-    HIPCHK(h, hipMemcpyAsync(h->d_S + kScalY, hs + kScalY, ncols * 8, hipMemcpyHostToDevice, c.s));
-    HIPCHK(h, launch_xupdate(Z, (long long)vb, ncols, h->d_S + kScalY, x, n, c.s));
-    if ((st = residual(c, b, x, V, Z, &beta2))) return st;
-    beta = sqrt(beta2);
-    c.info->rel_residual_true = beta / r0;
-    if (!isfinite(beta)) return FMP_ERR_BREAKDOWN;
-    if (beta <= tol * r0) { c.info->iterations = it; return FMP_OK; }
+    if (ncmax > 0) {
+      HIPCHK(h, hipMemcpyAsync(h->d_SD, SD, (size_t)ng * kSD * 8, hipMemcpyHostToDevice, c.s));
+      HIPCHK(h, launch_xupdate(Z, (long long)vb, ncmax, h->d_SD + kSDY, kSD, x, G.map, c.s));
+    }
+    if ((st = residual(c, b, x, V, Z, rrd, &tot))) return st;
+    all_done = true;
+    for (int g = 0; g < ng; ++g) {
+      Arnoldi& A_ = grp[g];
+      if (A_.finished) continue;
+      const double r2 = group_rr(rrd, g);
+      if (!isfinite(r2)) return finish(it, FMP_ERR_BREAKDOWN);
+      A_.beta = sqrt(r2);
+      A_.finished = A_.beta <= tol * A_.r0;
+      all_done = all_done && A_.finished;
+    }
+    if (all_done) return finish(it, FMP_OK);
   }
-  c.info->iterations = it;
-  return FMP_NOT_CONVERGED;
+  return finish(it, FMP_NOT_CONVERGED);
 }
 
 }  // namespace
@@ -883,6 +1203,12 @@ extern "C" fmp_status fmp_solve(fmp_handle h, const double* b, double* x, const 
   if (o->max_iter < 1 || !(o->rtol > 0.0)) return FMP_ERR_INVALID_ARG;
   if (o->capture_count < 0 || (o->capture_count > 0 && (!o->capture || o->solver != 1)))
     return FMP_ERR_INVALID_ARG;
+  if (o->per_domain && o->capture_count > 0 && h->doms.size() > 1) return FMP_ERR_INVALID_ARG;
+  if (o->per_domain && h->doms.size() > 1 &&
+      (o->solver != 1 || (o->precond && h->learned_set))) {
+    h->err = "per-domain solves run FGMRES without the learned part";
+    return FMP_ERR_UNSUPPORTED;
+  }
   if (overlaps(b, x, h->len * 8)) return FMP_ERR_ALIAS;
   size_t need = 0;
   fmp_status st = fmp_solve_workspace(h, o, &need);

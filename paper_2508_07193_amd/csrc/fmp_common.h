@@ -65,6 +65,18 @@ constexpr int kStencilTX = 64, kStencilTY = 4, kStencilZC = 16;
 constexpr int kRedBlocks = 1024;
 constexpr int kMaxDots = 34;    // CGS: up to restart+1 basis vectors + ||w||^2
 
+// A reduction segment: the elements [e0, e1) of a vector, walked by blocks
+// [b0, b0 + nb) of the kRedBlocks grid.  Either one segment covers the whole
+// vector (one Krylov method on the concatenated system) or there is one
+// segment per domain (independent solves advanced in lockstep).  A segmented
+// launch reads a per-block copy of its block's segment; `grp` indexes
+// per-segment coefficient and flag arrays.
+struct SegDev {
+  long long e0, e1;
+  int b0, nb;
+  int grp, dom;   // dom = the domain holding e0 (walls are masked per domain)
+};
+
 // ---- launchers (defined in the .hip files) ---------------------------------
 hipError_t launch_curlcurl(const double* x, double* y, const DomainDev* doms,
                            const StencilTile* tiles, int ntiles, const double* eps,
@@ -102,25 +114,38 @@ struct DotPtrs {
   const double* b[8];
 };
 hipError_t launch_dots(const DotPtrs& p, int n, long long len, double* partials, hipStream_t s);
-// Multi-dot h_i = <V_i, w> (i < nv) and h_nv = <w, w>; V_i = V + i * ldv.
-hipError_t launch_mdot(const double* V, long long ldv, int nv, const double* w, long long len,
-                       double* partials, hipStream_t s);
+// Multi-dot per segment g: h_{g,i} = <V_i, w>_g (i < nv) and h_{g,nv} = <w, w>_g;
+// V_i = V + i * ldv; map = per-block segments; segments whose act[grp] is 0
+// are skipped (partials 0).  act may be null (all active).
+hipError_t launch_mdot(const double* V, long long ldv, int nv, const double* w,
+                       const SegDev* map, const int* act, double* partials, hipStream_t s);
 // Final fixed-order reduction of `n` partial columns into out[0..n); post-op
 // codes run on thread 0 after the sums (see fmp_krylov.hip).
 hipError_t launch_reduce(const double* partials, int n, double* out, int post, double* S,
                          hipStream_t s);
-// w -= sum_i h_i V_i, partial ||w||^2 into partials (n = 1).
-hipError_t launch_mupdate(const double* V, long long ldv, int nv, const double* h, double* w,
-                          long long len, double* partials, hipStream_t s);
-// x += sum_i y_i Z_i.
-hipError_t launch_xupdate(const double* Z, long long ldz, int nz, const double* y, double* x,
-                          long long len, hipStream_t s);
+// Per-segment fixed-order reduction: out[g * ostride + i] for i < n, g < nseg.
+hipError_t launch_reduce_seg(const double* partials, int n, const SegDev* segs, int nseg,
+                             double* out, int ostride, hipStream_t s);
+// w -= sum_i h_{g,i} V_i on segment g (h_g = h + grp * hld), partial ||w||^2.
+hipError_t launch_mupdate(const double* V, long long ldv, int nv, const double* h, int hld,
+                          double* w, const SegDev* map, const int* act, double* partials,
+                          hipStream_t s);
+// x += sum_i y_{g,i} Z_i on segment g (y_g = y + grp * yld).
+hipError_t launch_xupdate(const double* Z, long long ldz, int nz, const double* y, int yld,
+                          double* x, const SegDev* map, hipStream_t s);
 hipError_t launch_axpby(double a, const double* x, double b, const double* y, double* out,
                         long long len, hipStream_t s);   // out = a x + b y
 hipError_t launch_scale_copy(const double* x, double a, double* out, long long len,
                              hipStream_t s);              // out = a x
-hipError_t launch_sub_norm(const double* b, const double* y, double* r, long long len,
-                           double* partials, hipStream_t s);  // r = b - y, partial ||r||^2
+// out = fac[grp] x on each segment (in place allowed).
+hipError_t launch_scale_seg(const double* x, const double* fac, double* out, const SegDev* map,
+                            hipStream_t s);
+// r = b - y with every PEC-wall slot set to 0, partial ||r||^2 per block;
+// map must hold one segment per domain.
+hipError_t launch_sub_norm(const double* b, const double* y, double* r, const SegDev* map,
+                           const DomainDev* doms, double* partials, hipStream_t s);
+// Set the PEC-wall slots of x to 0.
+hipError_t launch_zero_walls(double* x, const DomainDev* doms, int ndom, hipStream_t s);
 // BiCGSTAB fused steps (scalars live in device array S; see fmp_krylov.hip).
 hipError_t launch_bicg_p(const double* r, double* p, const double* v, const double* S,
                          long long len, hipStream_t s);

@@ -21,6 +21,14 @@ struct fmp_ctx {
   std::vector<BoxDev> boxes;
   std::vector<long long> offsets;
   std::vector<Launch> launches;
+  // batch planning: boxes in class order, their first pass-A / pass-B work
+  // items (one extra entry at the end), the staging capacity per W buffer
+  // (elements) and the current plan's knobs
+  std::vector<int> order, wa0, wb0;
+  long long w_cap = 0;
+  int batch = 0;               // boxes per batch
+  int nstreams = 2;            // 1 = batches in order on the caller's stream
+  bool tunable = false;
   int prec = 0;
   int overlap = 1;
   bool precond_ok = true;      // every box side has a compiled transform class
@@ -56,6 +64,20 @@ struct fmp_ctx {
   float* d_b2 = nullptr;
   float* d_b3 = nullptr;
   double* h_S = nullptr;       // pinned host mirror of scalars
+  // reduction segments: one over the whole vector, one per domain
+  fmp::SegDev* d_map_glob = nullptr;   // per block (kRedBlocks)
+  fmp::SegDev* d_segs_glob = nullptr;  // 1
+  fmp::SegDev* d_map_dom = nullptr;    // per block (kRedBlocks)
+  fmp::SegDev* d_segs_dom = nullptr;   // one per domain
+  std::vector<long long> seg_len;      // elements per domain segment
+  // per-group Krylov scalars (group = the whole system, or one domain):
+  // kSD doubles per group, then the group scale factors and activity flags
+  double* d_SD = nullptr;
+  double* d_fac = nullptr;
+  int* d_act = nullptr;
+  double* h_SD = nullptr;              // pinned mirror of d_SD, d_fac, d_act
+  double* h_fac = nullptr;
+  int* h_act = nullptr;
   // captured preconditioner applies, keyed by (r, z, learned part active)
   struct Graph {
     const double* r;

@@ -61,10 +61,26 @@ __global__ __launch_bounds__(kThreads) void k_dots(DotPtrs P, int n, long long l
 
 // Multi-vector kernels.  They are instantiated for the exact number of basis
 // vectors (1..33): an unrolled loop guarded by a runtime count issues its
-// loads in small groups and loses about a quarter of the bandwidth.  Each
-// thread walks 16-byte pairs of doubles with a grid stride; a trailing odd
-// element is handled by thread 0 of the last block.
+// loads in small groups and loses about a quarter of the bandwidth.
+//
+// Each block reads its segment (SegDev) and walks the segment's 16-byte pairs
+// of doubles with the segment's block stride; thread 0 of the segment's first
+// and last block take an odd leading and trailing element.  With one segment
+// over the whole vector this is a plain grid-stride walk.
 typedef double dbl2 __attribute__((ext_vector_type(2)));
+
+template <class P, class E>
+__device__ __forceinline__ void seg_walk2(const SegDev& sg, P&& pair, E&& one) {
+  const long long pa = (sg.e0 + 1) >> 1, pb = sg.e1 >> 1;
+  const long long stride = (long long)sg.nb * kThreads;
+  for (long long p = pa + (long long)((int)blockIdx.x - sg.b0) * kThreads + threadIdx.x; p < pb;
+       p += stride)
+    pair(p);
+  if (threadIdx.x == 0) {
+    if ((sg.e0 & 1) && (int)blockIdx.x == sg.b0) one(sg.e0);
+    if ((sg.e1 & 1) && (int)blockIdx.x == sg.b0 + sg.nb - 1) one(sg.e1 - 1);
+  }
+}
 
 // basis vectors are streamed once per pass: non-temporal loads
 __device__ __forceinline__ dbl2 ld_stream(const double* __restrict__ base, long long p) {
@@ -73,108 +89,163 @@ __device__ __forceinline__ dbl2 ld_stream(const double* __restrict__ base, long 
 
 template <int NV>
 __global__ __launch_bounds__(kThreads) void k_mdot(const double* __restrict__ V, long long ldv,
-                                                   const double* __restrict__ w, long long len,
+                                                   const double* __restrict__ w,
+                                                   const SegDev* __restrict__ map,
+                                                   const int* __restrict__ act,
                                                    double* __restrict__ partials) {
+  const SegDev sg = map[blockIdx.x];
   double acc[NV + 1];
 #pragma unroll
   for (int i = 0; i <= NV; ++i) acc[i] = 0.0;
-  const long long np = len >> 1, stride = (long long)gridDim.x * kThreads;
-  const dbl2* __restrict__ w2 = reinterpret_cast<const dbl2*>(w);
-  for (long long p = (long long)blockIdx.x * kThreads + threadIdx.x; p < np; p += stride) {
-    const dbl2 we = w2[p];
+  if (!act || act[sg.grp]) {
+    const dbl2* __restrict__ w2 = reinterpret_cast<const dbl2*>(w);
+    seg_walk2(
+        sg,
+        [&](long long p) {
+          const dbl2 we = w2[p];
 #pragma unroll
-    for (int i = 0; i < NV; ++i) {
-      const dbl2 v = ld_stream(V + i * ldv, p);
-      acc[i] = __builtin_fma(v.x, we.x, __builtin_fma(v.y, we.y, acc[i]));
-    }
-    acc[NV] = __builtin_fma(we.x, we.x, __builtin_fma(we.y, we.y, acc[NV]));
-  }
-  if ((len & 1) && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
-    const long long e = len - 1;
-    const double we = w[e];
+          for (int i = 0; i < NV; ++i) {
+            const dbl2 v = ld_stream(V + i * ldv, p);
+            acc[i] = __builtin_fma(v.x, we.x, __builtin_fma(v.y, we.y, acc[i]));
+          }
+          acc[NV] = __builtin_fma(we.x, we.x, __builtin_fma(we.y, we.y, acc[NV]));
+        },
+        [&](long long e) {
+          const double we = w[e];
 #pragma unroll
-    for (int i = 0; i < NV; ++i) acc[i] = __builtin_fma(V[i * ldv + e], we, acc[i]);
-    acc[NV] = __builtin_fma(we, we, acc[NV]);
+          for (int i = 0; i < NV; ++i) acc[i] = __builtin_fma(V[i * ldv + e], we, acc[i]);
+          acc[NV] = __builtin_fma(we, we, acc[NV]);
+        });
   }
   block_store<NV + 1>(acc, NV + 1, partials);   // <w,w> lands in column NV
 }
 
 template <int NV>
 __global__ __launch_bounds__(kThreads) void k_mupdate(const double* __restrict__ V, long long ldv,
-                                                      const double* __restrict__ h,
-                                                      double* __restrict__ w, long long len,
+                                                      const double* __restrict__ h, int hld,
+                                                      double* __restrict__ w,
+                                                      const SegDev* __restrict__ map,
+                                                      const int* __restrict__ act,
                                                       double* __restrict__ partials) {
-  double hh[NV];
-#pragma unroll
-  for (int i = 0; i < NV; ++i) hh[i] = h[i];
+  const SegDev sg = map[blockIdx.x];
   double acc[1] = {0.0};
-  const long long np = len >> 1, stride = (long long)gridDim.x * kThreads;
-  dbl2* __restrict__ w2 = reinterpret_cast<dbl2*>(w);
-  for (long long p = (long long)blockIdx.x * kThreads + threadIdx.x; p < np; p += stride) {
-    dbl2 we = w2[p];
+  if (!act || act[sg.grp]) {
+    double hh[NV];
 #pragma unroll
-    for (int i = 0; i < NV; ++i) {
-      const dbl2 v = reinterpret_cast<const dbl2*>(V + i * ldv)[p];
-      we.x = __builtin_fma(-hh[i], v.x, we.x);
-      we.y = __builtin_fma(-hh[i], v.y, we.y);
-    }
-    w2[p] = we;
-    acc[0] = __builtin_fma(we.x, we.x, __builtin_fma(we.y, we.y, acc[0]));
-  }
-  if ((len & 1) && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
-    const long long e = len - 1;
-    double we = w[e];
+    for (int i = 0; i < NV; ++i) hh[i] = h[sg.grp * hld + i];
+    dbl2* __restrict__ w2 = reinterpret_cast<dbl2*>(w);
+    seg_walk2(
+        sg,
+        [&](long long p) {
+          dbl2 we = w2[p];
 #pragma unroll
-    for (int i = 0; i < NV; ++i) we = __builtin_fma(-hh[i], V[i * ldv + e], we);
-    w[e] = we;
-    acc[0] = __builtin_fma(we, we, acc[0]);
+          for (int i = 0; i < NV; ++i) {
+            const dbl2 v = reinterpret_cast<const dbl2*>(V + i * ldv)[p];
+            we.x = __builtin_fma(-hh[i], v.x, we.x);
+            we.y = __builtin_fma(-hh[i], v.y, we.y);
+          }
+          w2[p] = we;
+          acc[0] = __builtin_fma(we.x, we.x, __builtin_fma(we.y, we.y, acc[0]));
+        },
+        [&](long long e) {
+          double we = w[e];
+#pragma unroll
+          for (int i = 0; i < NV; ++i) we = __builtin_fma(-hh[i], V[i * ldv + e], we);
+          w[e] = we;
+          acc[0] = __builtin_fma(we, we, acc[0]);
+        });
   }
   block_store<1>(acc, 1, partials);
 }
 
 template <int NV>
 __global__ __launch_bounds__(kThreads) void k_xupdate(const double* __restrict__ Z, long long ldz,
-                                                      const double* __restrict__ y,
-                                                      double* __restrict__ x, long long len) {
+                                                      const double* __restrict__ y, int yld,
+                                                      double* __restrict__ x,
+                                                      const SegDev* __restrict__ map) {
+  const SegDev sg = map[blockIdx.x];
   double yy[NV];
 #pragma unroll
-  for (int i = 0; i < NV; ++i) yy[i] = y[i];
-  const long long np = len >> 1, stride = (long long)gridDim.x * kThreads;
+  for (int i = 0; i < NV; ++i) yy[i] = y[sg.grp * yld + i];
   dbl2* __restrict__ x2 = reinterpret_cast<dbl2*>(x);
-  for (long long p = (long long)blockIdx.x * kThreads + threadIdx.x; p < np; p += stride) {
-    dbl2 xe = x2[p];
+  seg_walk2(
+      sg,
+      [&](long long p) {
+        dbl2 xe = x2[p];
 #pragma unroll
-    for (int i = 0; i < NV; ++i) {
-      const dbl2 v = ld_stream(Z + i * ldz, p);
-      xe.x = __builtin_fma(yy[i], v.x, xe.x);
-      xe.y = __builtin_fma(yy[i], v.y, xe.y);
-    }
-    x2[p] = xe;
-  }
-  if ((len & 1) && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
-    const long long e = len - 1;
-    double xe = x[e];
+        for (int i = 0; i < NV; ++i) {
+          const dbl2 v = ld_stream(Z + i * ldz, p);
+          xe.x = __builtin_fma(yy[i], v.x, xe.x);
+          xe.y = __builtin_fma(yy[i], v.y, xe.y);
+        }
+        x2[p] = xe;
+      },
+      [&](long long e) {
+        double xe = x[e];
 #pragma unroll
-    for (int i = 0; i < NV; ++i) xe = __builtin_fma(yy[i], Z[i * ldz + e], xe);
-    x[e] = xe;
-  }
+        for (int i = 0; i < NV; ++i) xe = __builtin_fma(yy[i], Z[i * ldz + e], xe);
+        x[e] = xe;
+      });
 }
 
 // same update for operands that are not 16-byte aligned
 template <int NV>
 __global__ __launch_bounds__(kThreads) void k_xupdate1(const double* __restrict__ Z, long long ldz,
                                                        int nz, const double* __restrict__ y,
-                                                       double* __restrict__ x, long long len) {
+                                                       int yld, double* __restrict__ x,
+                                                       const SegDev* __restrict__ map) {
+  const SegDev sg = map[blockIdx.x];
   double yy[NV];
 #pragma unroll
-  for (int i = 0; i < NV; ++i) yy[i] = (i < nz) ? y[i] : 0.0;
-  const long long stride = (long long)gridDim.x * kThreads;
-  for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < len; e += stride) {
+  for (int i = 0; i < NV; ++i) yy[i] = (i < nz) ? y[sg.grp * yld + i] : 0.0;
+  const long long stride = (long long)sg.nb * kThreads;
+  for (long long e = sg.e0 + (long long)((int)blockIdx.x - sg.b0) * kThreads + threadIdx.x;
+       e < sg.e1; e += stride) {
     double xe = x[e];
 #pragma unroll
     for (int i = 0; i < NV; ++i)
       if (i < nz) xe = __builtin_fma(yy[i], Z[i * ldz + e], xe);
     x[e] = xe;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_scale_seg(const double* __restrict__ x,
+                                                        const double* __restrict__ fac,
+                                                        double* __restrict__ out,
+                                                        const SegDev* __restrict__ map) {
+  const SegDev sg = map[blockIdx.x];
+  const double a = fac[sg.grp];
+  const dbl2* __restrict__ x2 = reinterpret_cast<const dbl2*>(x);
+  dbl2* __restrict__ o2 = reinterpret_cast<dbl2*>(out);
+  seg_walk2(
+      sg,
+      [&](long long p) {
+        const dbl2 v = x2[p];
+        dbl2 r;
+        r.x = a * v.x;
+        r.y = a * v.y;
+        o2[p] = r;
+      },
+      [&](long long e) { out[e] = a * x[e]; });
+}
+
+// Per-segment fixed-order reduction: thread t sums partial blocks b0 + t,
+// b0 + t + 256, ... of its segment; waves and then the block combine in order.
+__global__ __launch_bounds__(kThreads) void k_reduce_seg(const double* __restrict__ partials,
+                                                         int n, const SegDev* __restrict__ segs,
+                                                         double* __restrict__ out, int ostride) {
+  __shared__ double red[4];
+  const SegDev sg = segs[blockIdx.x];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  for (int i = 0; i < n; ++i) {
+    const double* p = partials + (long long)i * kRedBlocks + sg.b0;
+    double v = 0.0;
+    for (int k = t; k < sg.nb; k += kThreads) v += p[k];
+    v = wave_sum(v);
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    if (t == 0) out[(long long)blockIdx.x * ostride + i] = ((red[0] + red[1]) + red[2]) + red[3];
+    __syncthreads();
   }
 }
 
@@ -228,18 +299,60 @@ __global__ __launch_bounds__(kThreads) void k_scale_copy(const double* __restric
     out[e] = a * x[e];
 }
 
+// True 1 for a PEC-wall slot of a domain block: slot 0 along either node
+// axis of the slot's component (x index i, y index j, z index k).
+__device__ __forceinline__ bool wall_slot(const DomainDev& D, unsigned local) {
+  const unsigned nxy = (unsigned)D.nx * (unsigned)D.ny;
+  const unsigned cs = nxy * (unsigned)D.nz;
+  const unsigned q = local / cs;
+  const unsigned rem = local - q * cs;
+  const unsigned k = rem / nxy;
+  const unsigned rem2 = rem - k * nxy;
+  const unsigned j = rem2 / (unsigned)D.nx;
+  const unsigned i = rem2 - j * (unsigned)D.nx;
+  return q == 0 ? (j == 0 || k == 0) : q == 1 ? (i == 0 || k == 0) : (i == 0 || j == 0);
+}
+
 __global__ __launch_bounds__(kThreads) void k_sub_norm(const double* __restrict__ b,
                                                        const double* __restrict__ y,
-                                                       double* __restrict__ r, long long len,
+                                                       double* __restrict__ r,
+                                                       const SegDev* __restrict__ map,
+                                                       const DomainDev* __restrict__ doms,
                                                        double* __restrict__ partials) {
+  const SegDev sg = map[blockIdx.x];
+  const DomainDev D = doms[sg.dom];
   double acc[1] = {0.0};
-  const long long stride = (long long)kRedBlocks * kThreads;
-  for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < len; e += stride) {
-    const double v = b[e] - y[e];
+  const long long stride = (long long)sg.nb * kThreads;
+  for (long long e = sg.e0 + (long long)((int)blockIdx.x - sg.b0) * kThreads + threadIdx.x;
+       e < sg.e1; e += stride) {
+    const double v = wall_slot(D, (unsigned)(e - D.offset)) ? 0.0 : b[e] - y[e];
     r[e] = v;
     acc[0] = __builtin_fma(v, v, acc[0]);
   }
   block_store<1>(acc, 1, partials);
+}
+
+// blockIdx.y = 6 * domain + 2 * component + plane; plane 0 / 1 fixes the
+// component's first / second node axis at 0
+__global__ __launch_bounds__(kThreads) void k_zero_walls(double* __restrict__ x,
+                                                         const DomainDev* __restrict__ doms) {
+  const int d = blockIdx.y / 6, q = (blockIdx.y % 6) / 2, pl = blockIdx.y % 2;
+  const DomainDev D = doms[d];
+  const long long nxy = (long long)D.nx * D.ny, cs = nxy * D.nz;
+  double* __restrict__ xq = x + D.offset + q * cs;
+  // node axes: E_x (j, k), E_y (i, k), E_z (i, j); fix axis `fa` at 0
+  const int fa = q == 0 ? (pl ? 2 : 1) : q == 1 ? (pl ? 2 : 0) : (pl ? 1 : 0);
+  // the two free axes (a0 < a1): their extents and strides
+  const int n0 = fa == 0 ? D.ny : D.nx;
+  const int n1 = fa == 2 ? D.ny : D.nz;
+  const long long s0 = fa == 0 ? (long long)D.nx : 1;
+  const long long s1 = fa == 2 ? (long long)D.nx : nxy;
+  const long long cnt = (long long)n0 * n1;
+  for (long long t = (long long)blockIdx.x * kThreads + threadIdx.x; t < cnt;
+       t += (long long)gridDim.x * kThreads) {
+    const long long u = t % n0, v = t / n0;
+    xq[u * s0 + v * s1] = 0.0;
+  }
 }
 
 __global__ __launch_bounds__(kThreads) void k_bicg_p(const double* __restrict__ r,
@@ -294,37 +407,42 @@ int grid_for(long long len) {
 // compile-time dispatch of a runtime basis count to its instantiation
 template <int N>
 struct NV {
-  static void mdot(int nv, const double* V, long long ldv, const double* w, long long len,
-                   double* part, hipStream_t s) {
+  static void mdot(int nv, const double* V, long long ldv, const double* w, const SegDev* map,
+                   const int* act, double* part, hipStream_t s) {
     if (nv == N)
-      hipLaunchKernelGGL((k_mdot<N>), dim3(kRedBlocks), dim3(kThreads), 0, s, V, ldv, w, len, part);
-    else
-      NV<N - 1>::mdot(nv, V, ldv, w, len, part, s);
-  }
-  static void mupdate(int nv, const double* V, long long ldv, const double* h, double* w,
-                      long long len, double* part, hipStream_t s) {
-    if (nv == N)
-      hipLaunchKernelGGL((k_mupdate<N>), dim3(kRedBlocks), dim3(kThreads), 0, s, V, ldv, h, w, len,
+      hipLaunchKernelGGL((k_mdot<N>), dim3(kRedBlocks), dim3(kThreads), 0, s, V, ldv, w, map, act,
                          part);
     else
-      NV<N - 1>::mupdate(nv, V, ldv, h, w, len, part, s);
+      NV<N - 1>::mdot(nv, V, ldv, w, map, act, part, s);
   }
-  static void xupdate(int nz, const double* Z, long long ldz, const double* y, double* x,
-                      long long len, hipStream_t s) {
-    if (nz == N)
-      hipLaunchKernelGGL((k_xupdate<N>), dim3(kRedBlocks), dim3(kThreads), 0, s, Z, ldz, y, x, len);
+  static void mupdate(int nv, const double* V, long long ldv, const double* h, int hld, double* w,
+                      const SegDev* map, const int* act, double* part, hipStream_t s) {
+    if (nv == N)
+      hipLaunchKernelGGL((k_mupdate<N>), dim3(kRedBlocks), dim3(kThreads), 0, s, V, ldv, h, hld, w,
+                         map, act, part);
     else
-      NV<N - 1>::xupdate(nz, Z, ldz, y, x, len, s);
+      NV<N - 1>::mupdate(nv, V, ldv, h, hld, w, map, act, part, s);
+  }
+  static void xupdate(int nz, const double* Z, long long ldz, const double* y, int yld, double* x,
+                      const SegDev* map, hipStream_t s) {
+    if (nz == N)
+      hipLaunchKernelGGL((k_xupdate<N>), dim3(kRedBlocks), dim3(kThreads), 0, s, Z, ldz, y, yld, x,
+                         map);
+    else
+      NV<N - 1>::xupdate(nz, Z, ldz, y, yld, x, map, s);
   }
 };
 template <>
 struct NV<0> {
-  static void mdot(int, const double*, long long, const double*, long long, double*, hipStream_t) {}
-  static void mupdate(int, const double*, long long, const double*, double*, long long, double*,
-                      hipStream_t) {}
-  static void xupdate(int, const double*, long long, const double*, double*, long long,
+  static void mdot(int, const double*, long long, const double*, const SegDev*, const int*,
+                   double*, hipStream_t) {}
+  static void mupdate(int, const double*, long long, const double*, int, double*, const SegDev*,
+                      const int*, double*, hipStream_t) {}
+  static void xupdate(int, const double*, long long, const double*, int, double*, const SegDev*,
                       hipStream_t) {}
 };
+
+bool aligned16(const void* p) { return ((uintptr_t)p % 16) == 0; }
 
 }  // namespace
 
@@ -334,10 +452,11 @@ hipError_t launch_dots(const DotPtrs& p, int n, long long len, double* partials,
   return hipGetLastError();
 }
 
-hipError_t launch_mdot(const double* V, long long ldv, int nv, const double* w, long long len,
-                       double* partials, hipStream_t s) {
+hipError_t launch_mdot(const double* V, long long ldv, int nv, const double* w,
+                       const SegDev* map, const int* act, double* partials, hipStream_t s) {
   if (nv < 1 || nv + 1 > kMaxDots) return hipErrorInvalidValue;
-  NV<33>::mdot(nv, V, ldv, w, len, partials, s);
+  if (!aligned16(V) || !aligned16(w) || (ldv & 1)) return hipErrorInvalidValue;
+  NV<33>::mdot(nv, V, ldv, w, map, act, partials, s);
   return hipGetLastError();
 }
 
@@ -348,27 +467,50 @@ hipError_t launch_reduce(const double* partials, int n, double* out, int post, d
   return hipGetLastError();
 }
 
-hipError_t launch_mupdate(const double* V, long long ldv, int nv, const double* h, double* w,
-                          long long len, double* partials, hipStream_t s) {
-  if (nv < 1 || nv > 33) return hipErrorInvalidValue;
-  NV<33>::mupdate(nv, V, ldv, h, w, len, partials, s);
+hipError_t launch_reduce_seg(const double* partials, int n, const SegDev* segs, int nseg,
+                             double* out, int ostride, hipStream_t s) {
+  if (n < 1 || n > kMaxDots || nseg < 1 || nseg > kRedBlocks) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_reduce_seg, dim3(nseg), dim3(kThreads), 0, s, partials, n, segs, out,
+                     ostride);
   return hipGetLastError();
 }
 
-hipError_t launch_xupdate(const double* Z, long long ldz, int nz, const double* y, double* x,
-                          long long len, hipStream_t s) {
+hipError_t launch_mupdate(const double* V, long long ldv, int nv, const double* h, int hld,
+                          double* w, const SegDev* map, const int* act, double* partials,
+                          hipStream_t s) {
+  if (nv < 1 || nv > 33) return hipErrorInvalidValue;
+  if (!aligned16(V) || !aligned16(w) || (ldv & 1)) return hipErrorInvalidValue;
+  NV<33>::mupdate(nv, V, ldv, h, hld, w, map, act, partials, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_xupdate(const double* Z, long long ldz, int nz, const double* y, int yld,
+                          double* x, const SegDev* map, hipStream_t s) {
   if (nz < 1 || nz > 33) return hipErrorInvalidValue;
-  const bool aligned = ((uintptr_t)Z % 16 == 0) && ((uintptr_t)x % 16 == 0) && (ldz % 2 == 0);
-  if (aligned) {
-    NV<33>::xupdate(nz, Z, ldz, y, x, len, s);
+  if (aligned16(Z) && aligned16(x) && (ldz % 2 == 0)) {
+    NV<33>::xupdate(nz, Z, ldz, y, yld, x, map, s);
   } else {
-#define L(NVV) hipLaunchKernelGGL((k_xupdate1<NVV>), dim3(grid_for(len)), dim3(kThreads), 0, s, Z, ldz, nz, y, x, len)
+#define L(NVV) \
+  hipLaunchKernelGGL((k_xupdate1<NVV>), dim3(kRedBlocks), dim3(kThreads), 0, s, Z, ldz, nz, y, yld, x, map)
     if (nz <= 4) L(4);
     else if (nz <= 8) L(8);
     else if (nz <= 16) L(16);
     else L(33);
 #undef L
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_seg(const double* x, const double* fac, double* out, const SegDev* map,
+                            hipStream_t s) {
+  if (!aligned16(x) || !aligned16(out)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_scale_seg, dim3(kRedBlocks), dim3(kThreads), 0, s, x, fac, out, map);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_walls(double* x, const DomainDev* doms, int ndom, hipStream_t s) {
+  if (ndom < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_zero_walls, dim3(64, 6 * ndom), dim3(kThreads), 0, s, x, doms);
   return hipGetLastError();
 }
 
@@ -384,9 +526,10 @@ hipError_t launch_scale_copy(const double* x, double a, double* out, long long l
   return hipGetLastError();
 }
 
-hipError_t launch_sub_norm(const double* b, const double* y, double* r, long long len,
-                           double* partials, hipStream_t s) {
-  hipLaunchKernelGGL(k_sub_norm, dim3(kRedBlocks), dim3(kThreads), 0, s, b, y, r, len, partials);
+hipError_t launch_sub_norm(const double* b, const double* y, double* r, const SegDev* map,
+                           const DomainDev* doms, double* partials, hipStream_t s) {
+  hipLaunchKernelGGL(k_sub_norm, dim3(kRedBlocks), dim3(kThreads), 0, s, b, y, r, map, doms,
+                     partials);
   return hipGetLastError();
 }
 

@@ -258,10 +258,17 @@ def test_failure_paths():
     info = h.solve(b, x, solver="fgmres", rtol=1e-12, max_iter=1)
     assert info["status"] == "FMP_NOT_CONVERGED" and info["iterations"] == 1
     bn = b.clone()
-    bn[100] = float("nan")
+    bn[100] = float("nan")        # E_x slot (i, j, k) = (4, 6, 0): a wall, ignored
+    x = h.new_vector()
+    info = h.solve(bn, x, solver="bicgstab", rtol=1e-8, max_iter=50)
+    assert info["status"] == "FMP_OK"
+    bn[(5 * 16 + 5) * 16 + 5] = float("nan")   # E_x unknown at (5, 5, 5)
     x = h.new_vector()
     with pytest.raises(api.FlashMPError, match="BREAKDOWN"):
         h.solve(bn, x, solver="bicgstab", rtol=1e-8, max_iter=5)
+    x = h.new_vector()
+    with pytest.raises(api.FlashMPError, match="BREAKDOWN"):
+        h.solve(bn, x, solver="fgmres", rtol=1e-8, max_iter=5)
 
 
 # ------------------------------------------------------------------ full-size samples
@@ -354,3 +361,76 @@ def test_batch_of_uneven_domains_matches_oracle():
     x = h.new_vector()
     info = h.solve(r, x, solver="fgmres", rtol=1e-8, max_iter=300)
     assert info["status"] == "FMP_OK" and info["rel_residual_true"] <= 1e-8
+
+
+def test_per_domain_fgmres_matches_independent_oracle_solves():
+    """Independent FGMRES per domain, run in lockstep: each domain's step count,
+    residual and solution match an oracle FGMRES of that domain alone.  The
+    15^3 domain has odd length, so the later domains start at odd offsets."""
+    spec = [(16, 8, 2.0, 4, 31), (15, 5, 0.5, 5, 32), (12, 12, 8.0, 0, 33), (20, 10, 3.0, 5, 34)]
+    doms, probs = [], []
+    for n, sub, c, blk, seed in spec:
+        P = problem(n, sub, c, blk, seed)
+        probs.append(P)
+        doms.append(dict(nx=n, ny=n, nz=n, c=c, eps=P["eps"], eps_block=blk, sub=sub))
+    h = api.Handle(doms, device=DEV)
+    b = torch.cat([dev(P["rhs"]) for P in probs])
+    x = h.new_vector()
+    info = h.solve(b, x, solver="fgmres", restart=30, rtol=1e-8, max_iter=300, per_domain=True)
+    assert info["status"] == "FMP_OK"
+    xs = x.cpu().numpy()
+    for d, P in enumerate(probs):
+        A, Af, Mf = _oracle_ops(P)
+        xo, io = krylov.fgmres(Af, P["rhs"], M=Mf, tol=1e-8, restart=30)
+        assert abs(info["domain_iterations"][d] - io["iterations"]) <= 1, (d, info, io["iterations"])
+        assert info["domain_rel_residual"][d] <= 1e-8
+        xd = xs[h.offsets[d]:h.offsets[d + 1]].reshape(P["rhs"].shape)
+        res = np.linalg.norm(yee.from_padded(P["rhs"]) - A @ yee.from_padded(xd)) / np.linalg.norm(P["rhs"])
+        assert res <= 1.5e-8, d
+        assert relmax(xd, xo) < 1e-6, d
+    assert info["iterations"] == max(info["domain_iterations"])
+    with pytest.raises(api.FlashMPError, match="UNSUPPORTED"):
+        h.solve(b, x, solver="bicgstab", rtol=1e-8, per_domain=True)
+
+
+def test_solve_ignores_wall_slots_of_b_and_x0():
+    P = problem(16, 8, 2.0, 4, seed=41)
+    h = handle_for(P)
+    shape = P["rhs"].shape
+    wall = ~yee.wall_mask(16, 16, 16)   # True on PEC-wall slots
+    b = P["rhs"].copy()
+    assert np.all(b[wall] == 0.0)
+    x_clean = h.new_vector()
+    i_clean = h.solve(dev(b), x_clean, solver="fgmres", rtol=1e-8)
+    rng = np.random.default_rng(5)
+    bg = b.copy()
+    bg[wall] = rng.normal(size=int(wall.sum())) * 1e3
+    x0 = np.zeros(shape)
+    x0[wall] = 7.0
+    x = dev(x0)
+    i_g = h.solve(dev(bg), x, solver="fgmres", rtol=1e-8)
+    assert i_g["iterations"] == i_clean["iterations"]
+    xs = host(x, shape)
+    assert np.all(xs[wall] == 0.0)
+    assert np.array_equal(xs, host(x_clean, shape))
+
+
+def test_autotune_keeps_results_bitwise():
+    """fmp_autotune only changes the schedule: z is bit-identical before and after."""
+    rng = np.random.default_rng(51)
+    spec = [(24, 24, 1.5), (16, 16, 0.5), (12, 12, 8.0), (48, 24, 3.0), (32, 16, 2.0)]
+    doms = [dict(nx=n, ny=n, nz=n, c=c, sub=sub) for n, sub, c in spec]
+    r = torch.cat([dev(inputs.normal_rhs(rng, n, n, n)) for n, _, _ in spec])
+    for prec, graph in (("fp32", True), ("fp64", False)):
+        h = api.Handle(doms, precision=prec, device=DEV, batch_boxes=-1, use_graph=graph)
+        z0 = h.new_vector()
+        h.apply_precond(r, z0)
+        tune = h.autotune(r, h.new_vector())
+        assert sum(t["chosen"] for t in tune) == 1 and all(t["apply_ms"] > 0 for t in tune)
+        assert {t["streams"] for t in tune} == {1, 2}
+        z1 = h.new_vector()
+        h.apply_precond(r, z1)
+        assert torch.equal(z0, z1), prec
+    h = api.Handle(doms[:1], device=DEV)
+    with pytest.raises(api.FlashMPError, match="UNSUPPORTED"):
+        h.autotune(r[:h.length].contiguous())
