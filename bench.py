@@ -56,44 +56,55 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(P, iters, sample_boxes=12):
+def cpu_baseline(P, iters, sample_boxes=512):
     """Time the CPU oracle on a bounded sample of one FGMRES iteration's work and scale it.
 
-    Sample: `sample_boxes` of the 512 subdomain solves (scaled to 512), one
-    sparse A x on a 64^3 sub-grid (scaled by unknown count), and one dot and
-    one axpy on full 256^3 vectors (scaled to the CGS work of an average
-    Arnoldi step, j = 15: 2j + 5 vector passes).  Reported as the estimated
-    time-to-solution for the same iteration count as the GPU run.
+    Sample: `sample_boxes` of the 512 subdomain solves (all of them by
+    default: one whole preconditioner apply), three sparse A x on a 64^3
+    sub-grid (scaled by unknown count), and ten dots and axpys on full 256^3
+    vectors (scaled to the CGS work of an average Arnoldi step, j = 15:
+    2j + 5 vector passes).  Reported as the estimated time-to-solution for the
+    same iteration count as the GPU run; `cores` is the BLAS thread count the
+    oracle's numpy calls use.
     """
     from oracle import ras, yee
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        cores = os.cpu_count()
     n = P["nx"]
     eps_cell = yee.expand_eps(P["eps"], P["eps_block"], n, n, n)
     nsub = (n // P["sub"][0]) ** 3
     which = list(np.linspace(0, nsub - 1, sample_boxes).astype(int))
     t0 = time.perf_counter()
     ras.ras_apply_subset(P["rhs"], P["c"], P["sub"], 1, eps_cell, which)
-    t_pre = (time.perf_counter() - t0) * nsub / sample_boxes
+    m_pre = time.perf_counter() - t0
+    t_pre = m_pre * nsub / sample_boxes
     m = 64
     A = yee.assemble_A(m, m, m, P["c"], eps_cell[:m, :m, :m])
     xs = yee.from_padded(P["rhs"][:, :m, :m, :m])
     t0 = time.perf_counter()
     for _ in range(3):
         A @ xs
-    t_spmv = (time.perf_counter() - t0) / 3 * (yee.n_unknowns(n, n, n) / xs.size)
+    m_spmv = time.perf_counter() - t0
+    t_spmv = m_spmv / 3 * (yee.n_unknowns(n, n, n) / xs.size)
     a = P["rhs"].ravel()
     b = np.roll(a, 1)
     t0 = time.perf_counter()
-    float(np.dot(a, b))
-    c = a + 0.5 * b
-    t_vec = (time.perf_counter() - t0) / 2
+    for _ in range(10):
+        float(np.dot(a, b))
+        c = a + 0.5 * b
+    m_vec = time.perf_counter() - t0
+    t_vec = m_vec / 20
     del c
     per_it = t_pre + t_spmv + (2 * 15 + 5) * t_vec
     total = per_it * iters
-    return dict(value=round(total * 1e3, 1), unit="ms", cores=os.cpu_count(), kind="oracle",
-                sample=(f"{sample_boxes}/{nsub} subdomain solves, one 64^3 sparse A x, one dot + "
-                        f"axpy on 256^3 vectors, scaled to {iters} FGMRES iterations "
+    return dict(value=round(total * 1e3, 1), unit="ms", cores=cores, kind="oracle",
+                sample=(f"{sample_boxes}/{nsub} subdomain solves, three 64^3 sparse A x, ten dots "
+                        f"and axpys on 256^3 vectors, scaled to {iters} FGMRES iterations "
                         f"({per_it * 1e3:.0f} ms per iteration)"),
-                seconds_measured=round((t_pre * sample_boxes / nsub) + t_spmv / 1 + t_vec, 2))
+                seconds_measured=round(m_pre + m_spmv + m_vec, 2))
 
 
 def learned_leg(args, dev, log):
@@ -107,7 +118,9 @@ def learned_leg(args, dev, log):
     P = inputs.make_problem("c5")
     n = P["nx"]
     dom = dict(nx=n, ny=n, nz=n, c=P["c"], eps=P["eps"], eps_block=P["eps_block"], sub=P["sub"])
-    h = api.Handle([dom], overlap=1, precision="fp64", use_learned=True, device=dev)
+    h = api.Handle([dom], overlap=1, precision="fp64", use_learned=True, device=dev,
+                   batch_boxes=-1, use_graph=True)
+    h.autotune()
     t0 = time.perf_counter()
     X, Y = learned.generate_pairs(h, (n, n, n), args.pairs_rhs, args.pairs_per_rhs, 1005, log=log)
     t_pairs = time.perf_counter() - t0
@@ -227,8 +240,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--learned", type=int, default=1, help="run the C5 learned-correction leg")
     ap.add_argument("--batch", type=int, default=1, help="run the 64-domain batch leg")
-    ap.add_argument("--pairs-rhs", type=int, default=200)
-    ap.add_argument("--pairs-per-rhs", type=int, default=10)
+    ap.add_argument("--pairs-rhs", type=int, default=100)
+    ap.add_argument("--pairs-per-rhs", type=int, default=20)
     ap.add_argument("--epochs", type=int, default=150)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -278,8 +291,16 @@ def main():
         e1.synchronize()
         return e0.elapsed_time(e1) / reps
 
+    def tuned_handle(prec):
+        hh = api.Handle([dom], overlap=1, precision=prec, device=dev, batch_boxes=-1,
+                        use_graph=True)
+        t = hh.autotune(b)
+        c = [e for e in t if e["chosen"]][0]
+        log(f"[{prec}] autotune: {[(e['batch_boxes'], e['streams'], round(e['apply_ms'], 4)) for e in t]}")
+        return hh, dict(batch_boxes=c["batch_boxes"], streams=c["streams"], graph=True)
+
     # ---------------- plain FP64 FlashMP
-    h = api.Handle([dom], overlap=1, precision="fp64", device=dev)
+    h, plan64 = tuned_handle("fp64")
     log(f"handle ready: workspace {h.ws.numel() / 2**20:.0f} MiB, vector {h.length} doubles")
     x64, info64, tts64 = run_solves(h, args.steps, args.warmup, "fp64")
     z = h.new_vector()
@@ -336,6 +357,7 @@ def main():
         "rel_residual_true": info64["rel_residual_true"],
         "precond_applies_per_s": round(1e3 / t_pre, 1),
         "precond_ms": round(t_pre, 4),
+        "precond_plan": plan64,
         "precond_hbm_gbs_min_traffic": round(pre_bytes / (t_pre * 1e-3) / 1e9, 1),
         "spmv_ms": round(t_spmv, 4),
         "roofline": roofs[dominant],
@@ -351,7 +373,7 @@ def main():
 
     for prec in [v for v in args.variants.split(",") if v]:
         try:
-            hv = api.Handle([dom], overlap=1, precision=prec, device=dev)
+            hv, planv = tuned_handle(prec)
             xv, infov, ttsv = run_solves(hv, max(1, args.steps), args.warmup, prec)
             zv = hv.new_vector()
             tpv = time_events(lambda: hv.apply_precond(b, zv), 10)
@@ -361,7 +383,7 @@ def main():
                                          rel_residual_true=infov["rel_residual_true"],
                                          precond_applies_per_s=round(1e3 / tpv, 1),
                                          precond_ms=round(tpv, 4),
-                                         rel_err_vs_fp64_solution=err,
+                                         rel_err_vs_fp64_solution=err, precond_plan=planv,
                                          speedup_vs_fp64=round(tts64 / ttsv, 3))
             del hv
             torch.cuda.empty_cache()

@@ -37,11 +37,12 @@ constexpr int kScalW = 64;      // ||w||^2
 constexpr int kScalY = 128;     // FGMRES update coefficients
 constexpr int kScalJ = 200;     // learned-correction judge: ||v - w||^2, ||v - w + A d||^2
 // per-group scalar block (kSD doubles per group)
-constexpr int kSD = 128;
+constexpr int kSD = 192;
 constexpr int kSDH = 0;         // h column and ||w||^2 before the update (<= 34)
 constexpr int kSDW = 40;        // ||w||^2 after the update
 constexpr int kSDY = 48;        // update coefficients y (<= 33)
 constexpr int kSDR = 96;        // ||r||^2 of a residual
+constexpr int kSDS = 128;       // squared scales s_i^2 of the stored basis (<= 33)
 
 struct Parts {
   int own0, own1, box0, box1;
@@ -181,30 +182,31 @@ static fmp_status precond_apply(fmp_ctx* h, const double* r, double* z, hipStrea
 static fmp_status precond_launches(fmp_ctx* h, const double* r, double* z, hipStream_t s,
                                    const double* coarse) {
   const int prec = h->prec;
-  // Two or more batches: batch k runs on private stream k % 2 with staging
-  // buffer k % 2, so the gather pass of one batch overlaps the solve passes
-  // of the previous one.  Batches write disjoint parts of z.
-  const bool two = h->launches.size() > 1 && h->d_Wb && h->nstreams == 2;
-  hipStream_t bs[2] = {s, s};
-  if (two) {
-    for (int i = 0; i < 2; ++i)
+  // Several batches: batch k runs on private stream k % ns with staging
+  // buffer k % ns, so the passes of up to ns batches overlap.  Batches write
+  // disjoint parts of z.
+  const int ns = std::min(std::min(h->nstreams, h->n_wbuf), (int)h->launches.size());
+  hipStream_t bs[fmp_ctx::kMaxStreams];
+  for (int i = 0; i < fmp_ctx::kMaxStreams; ++i) bs[i] = s;
+  if (ns > 1) {
+    if (!h->ev_fork) HIPCHK(h, hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+    for (int i = 0; i < ns; ++i) {
       if (!h->bat_stream[i])
         HIPCHK(h, hipStreamCreateWithFlags(&h->bat_stream[i], hipStreamNonBlocking));
-    if (!h->ev_fork) {
-      HIPCHK(h, hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
-      HIPCHK(h, hipEventCreateWithFlags(&h->ev_join[0], hipEventDisableTiming));
-      HIPCHK(h, hipEventCreateWithFlags(&h->ev_join[1], hipEventDisableTiming));
+      if (!h->ev_join[i])
+        HIPCHK(h, hipEventCreateWithFlags(&h->ev_join[i], hipEventDisableTiming));
     }
     HIPCHK(h, hipEventRecord(h->ev_fork, s));
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < ns; ++i) {
       HIPCHK(h, hipStreamWaitEvent(h->bat_stream[i], h->ev_fork, 0));
       bs[i] = h->bat_stream[i];
     }
   }
   for (size_t k = 0; k < h->launches.size(); ++k) {
     const Launch& L = h->launches[k];
-    const hipStream_t st = bs[k & 1];
-    void* W = (two && (k & 1)) ? h->d_Wb : h->d_W;
+    const int slot = ns > 1 ? (int)(k % ns) : 0;
+    const hipStream_t st = bs[slot];
+    void* W = h->d_Wk[slot];
     if (prec == FMP_BF16) {
       HIPCHK(h, launch_mfma_pass_a(L.cls, r, W, h->d_boxes, h->d_doms,
                                    h->d_work_a + L.a0, L.na, (const __hip_bfloat16*)h->d_tab, st));
@@ -222,8 +224,8 @@ static fmp_status precond_launches(fmp_ctx* h, const double* r, double* z, hipSt
                               L.na, h->d_tab, coarse, h->nsub, st));
     }
   }
-  if (two) {
-    for (int i = 0; i < 2; ++i) {
+  if (ns > 1) {
+    for (int i = 0; i < ns; ++i) {
       HIPCHK(h, hipEventRecord(h->ev_join[i], bs[i]));
       HIPCHK(h, hipStreamWaitEvent(s, h->ev_join[i], 0));
     }
@@ -521,10 +523,11 @@ fmp_status fmp_setup_subdomains(const fmp_domain_desc* domains, int32_t n_domain
   const size_t o_SD = cur; cur = align_up(cur + sd_bytes);
   const size_t o_learn = cur;
   if (h->use_learned) cur = align_up(cur + fmp_coarse_workspace(h->nsub, 512));
-  const size_t o_W = cur; cur = align_up(cur + (size_t)w_batch_max * wsz);
-  const bool two_w = h->launches.size() > 1 || h->tunable;
-  const size_t o_W2 = cur;
-  if (two_w) cur = align_up(cur + (size_t)w_batch_max * wsz);
+  // staging buffers: one per batch stream (a tunable handle keeps room for
+  // the most streams fmp_autotune tries)
+  h->n_wbuf = h->tunable ? fmp_ctx::kMaxStreams : (h->launches.size() > 1 ? 2 : 1);
+  const size_t o_W = cur;
+  cur = align_up(cur + (size_t)h->n_wbuf * align_up((size_t)w_batch_max * wsz));
   const size_t need = cur;
 
   if (!ws) {
@@ -552,8 +555,9 @@ fmp_status fmp_setup_subdomains(const fmp_domain_desc* domains, int32_t n_domain
   h->d_SD = (double*)(base + o_SD);
   h->d_fac = h->d_SD + (size_t)n_domains * kSD;
   h->d_act = (int*)(h->d_fac + n_domains);
-  h->d_W = base + o_W;
-  if (two_w) h->d_Wb = base + o_W2;
+  for (int i = 0; i < h->n_wbuf; ++i)
+    h->d_Wk[i] = base + o_W + (size_t)i * align_up((size_t)w_batch_max * wsz);
+  h->d_W = h->d_Wk[0];
   if (h->use_learned) fmp_coarse_bind(h.get(), base + o_learn);
 
   // typed tables
@@ -612,7 +616,7 @@ fmp_status fmp_destroy(fmp_handle h) {
   if (h->h_SD) (void)hipHostFree(h->h_SD);
   for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.exec);
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
-  for (int i = 0; i < 2; ++i) {
+  for (int i = 0; i < fmp_ctx::kMaxStreams; ++i) {
     if (h->bat_stream[i]) (void)hipStreamDestroy(h->bat_stream[i]);
     if (h->ev_join[i]) (void)hipEventDestroy(h->ev_join[i]);
   }
@@ -661,7 +665,8 @@ fmp_status fmp_autotune(fmp_handle h, const double* r, double* z, fmp_tune_entry
   struct Cand { int batch, ns; double ms; };
   std::vector<Cand> cands;
   for (int b : batches)
-    for (int ns = 1; ns <= 2; ++ns) cands.push_back({b, ns, 0.0});
+    for (int ns = 1; ns <= std::min(h->n_wbuf, fmp_ctx::kMaxStreams); ++ns)
+      cands.push_back({b, ns, 0.0});
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIPCHK(h, hipEventCreate(&e0));
   HIPCHK(h, hipEventCreate(&e1));
@@ -679,7 +684,7 @@ fmp_status fmp_autotune(fmp_handle h, const double* r, double* z, fmp_tune_entry
   fmp_status st = FMP_OK;
   for (Cand& c : cands) {
     if ((st = use(c.batch, c.ns)) != FMP_OK) break;
-    if (c.ns == 2 && h->launches.size() < 2) { c.ms = -1.0; continue; }   // same as 1 stream
+    if (c.ns > 1 && (int)h->launches.size() < c.ns) { c.ms = -1.0; continue; }   // no more overlap
     if ((st = precond_apply(h, r, z, s, coarse)) != FMP_OK) break;      // capture / warm up
     HIPCHK(h, hipEventRecord(e0, s));
     constexpr int kReps = 3;
@@ -836,10 +841,11 @@ hipError_t orth_dot(Ctx& c, const Groups& G, const int* act, double act_len, con
   return r;
 }
 hipError_t orth_update(Ctx& c, const Groups& G, const int* act, double act_len, const double* V,
-                       long long ldv, int nv, const double* hcoef, int hld, double* w) {
+                       long long ldv, int nv, const double* hcoef, const double* sc, int hld,
+                       double* w) {
   hipEvent_t e = c.begin();
   const hipError_t r =
-      launch_mupdate(V, ldv, nv, hcoef, hld, w, G.map, act, c.h->d_part, c.s);
+      launch_mupdate(V, ldv, nv, hcoef, sc, hld, w, G.map, act, c.h->d_part, c.s);
   c.end(Prof::UPD, e);
   c.info->n_orth_update++;
   c.info->bytes_orth_update += 8.0 * act_len * (nv + 2);
@@ -952,10 +958,13 @@ fmp_status bicgstab(Ctx& c, const double* b, double* x, double* ws) {
   return broke ? FMP_ERR_BREAKDOWN : FMP_NOT_CONVERGED;
 }
 
-// Arnoldi state of one group's FGMRES cycle.
+// Arnoldi state of one group's FGMRES cycle.  The basis is stored
+// unnormalised: v_i = s_i V_i, so no pass over the vector is spent on scaling;
+// the scales enter the coefficients instead (true h_ij = s_i s_j <V_i, W>,
+// update coefficients s_i^2 <V_i, W>, x update coefficients y_i s_i).
 struct Arnoldi {
   int m = 0;
-  std::vector<double> H, cs, sn, g, y;
+  std::vector<double> H, cs, sn, g, y, s;
   double r0 = 0.0, beta = 0.0;
   int ncols = 0;
   bool active = false;     // iterating in the current cycle
@@ -966,7 +975,9 @@ struct Arnoldi {
     H.assign((size_t)(m + 1) * m, 0.0);
     cs.assign(m, 0.0); sn.assign(m, 0.0); y.assign(m, 0.0);
     g.assign(m + 1, 0.0);
+    s.assign(m + 1, 0.0);
     g[0] = beta_;
+    s[0] = beta_ > 0.0 ? 1.0 / beta_ : 0.0;
     ncols = 0;
   }
   // append column j (h_0..h_j, h_{j+1} = hn), rotate it, return |g_{j+1}|
@@ -1057,36 +1068,62 @@ fmp_status fgmres(Ctx& c, const double* b, double* x, double* ws) {
       if (grp[g].active) t += glen[g];
     return t;
   };
-  // group scale factors and activity flags to the device
+  // host scalars (squared basis scales, update coefficients) and activity
+  // flags to the device
   int* act = h->h_act;
   auto push = [&]() -> hipError_t {
-    hipError_t e = hipMemcpyAsync(h->d_fac, h->h_fac, (size_t)ng * 8, hipMemcpyHostToDevice, c.s);
+    hipError_t e = hipMemcpyAsync(h->d_SD, SD, (size_t)ng * kSD * 8, hipMemcpyHostToDevice, c.s);
     if (e != hipSuccess) return e;
     return hipMemcpyAsync(h->d_act, act, (size_t)ng * 4, hipMemcpyHostToDevice, c.s);
   };
+  // Explicit scaling of a stored basis vector, per group: 0 for groups that
+  // stopped while others go on (their part of later vectors stays 0), s for
+  // groups whose stored norm 1/s left [1e-15, 1e15] (the reduced-precision
+  // transforms must not see under- or overflowing inputs), 1 (skipped) else.
+  auto fix_scale = [&](double* v, const std::vector<double>& fac) -> fmp_status {
+    bool any = false;
+    for (int g = 0; g < ng; ++g) {
+      h->h_fac[g] = fac[g];
+      any = any || fac[g] != 1.0;
+    }
+    if (!any) return FMP_OK;
+    HIPCHK(h, hipMemcpyAsync(h->d_fac, h->h_fac, (size_t)ng * 8, hipMemcpyHostToDevice, c.s));
+    HIPCHK(h, launch_scale_seg(v, h->d_fac, v, G.map, c.s));
+    return FMP_OK;
+  };
 
+  // the learned part stays on while the FP64 residual judge keeps accepting
+  // it; after kMaxRejects rejections in a row the solve continues without it
+  constexpr int kMaxRejects = 3;
+  bool use_learned = !per && c.o->precond != 0 && h->learned_set;
+  int rejects = 0;
   int it = 0;
   while (it < c.o->max_iter) {
-    // new cycle: v_0 = r / beta per group (0 for finished groups)
+    // new cycle: V_0 = r (stored unnormalised, s_0 = 1 / beta); finished
+    // groups get V_0 = 0
+    std::vector<double> fac(ng, 1.0);
     for (int g = 0; g < ng; ++g) {
       Arnoldi& A_ = grp[g];
       A_.active = !A_.finished;
-      A_.start(m, A_.beta);
-      h->h_fac[g] = A_.active ? 1.0 / A_.beta : 0.0;
+      A_.start(m, A_.active ? A_.beta : 0.0);
+      if (!A_.active) fac[g] = 0.0;
+      else if (A_.s[0] > 1e15 || A_.s[0] < 1e-15) { fac[g] = A_.s[0]; A_.s[0] = 1.0; }
+      SD[(size_t)g * kSD + kSDS] = A_.s[0] * A_.s[0];
       act[g] = A_.active ? 1 : 0;
     }
     HIPCHK(h, push());
-    HIPCHK(h, launch_scale_seg(V, h->d_fac, V, G.map, c.s));
+    if ((st = fix_scale(V, fac))) return st;
     for (int j = 0; j < m; ++j) {
       double* vj = V + (size_t)j * vb;
       double* zj = Z + (size_t)j * vb;
       double* w = V + (size_t)(j + 1) * vb;
-      const bool learned = !per && c.o->precond != 0 && h->learned_set;
+      const bool learned = use_learned;
       if ((st = M(c, vj, zj, learned))) return st;
       if ((st = A(c, zj, w))) return st;
       if (learned) {
         // the FP64 residual judges the correction: keep it only if
         // ||v - A z|| does not exceed the plain preconditioner's ||v - A z_RAS||
+        // (both sides carry the same basis scale)
         HIPCHK(h, fmp_coarse_judge(h, vj, w, h->d_part, c.s));
         HIPCHK(h, launch_reduce(h->d_part, 2, h->d_S + kScalJ, 0, h->d_S, c.s));
         HIPCHK(h, hipMemcpyAsync(hs + kScalJ, h->d_S + kScalJ, 16, hipMemcpyDeviceToHost, c.s));
@@ -1096,27 +1133,35 @@ fmp_status fgmres(Ctx& c, const double* b, double* x, double* ws) {
           c.info->n_precond++;
           if ((st = precond_apply(h, vj, zj, c.s, nullptr))) return st;
           if ((st = A(c, zj, w))) return st;
+          if (++rejects >= kMaxRejects) use_learned = false;
+        } else {
+          rejects = 0;
         }
       }
-      // classical Gram-Schmidt per group: h = V^T w (and ||w||^2), w -= V h, ||w||^2
+      // classical Gram-Schmidt per group on the stored vectors:
+      // h~ = V^T W (and ||W||^2), W -= V (s^2 h~), ||W||^2
       const double alen = active_len();
       HIPCHK(h, orth_dot(c, G, h->d_act, alen, V, (long long)vb, j + 1, w));
       HIPCHK(h, launch_reduce_seg(h->d_part, j + 2, G.segs, ng, h->d_SD + kSDH, kSD, c.s));
-      HIPCHK(h, orth_update(c, G, h->d_act, alen, V, (long long)vb, j + 1, h->d_SD + kSDH, kSD, w));
+      HIPCHK(h, orth_update(c, G, h->d_act, alen, V, (long long)vb, j + 1, h->d_SD + kSDH,
+                            h->d_SD + kSDS, kSD, w));
       HIPCHK(h, launch_reduce_seg(h->d_part, 1, G.segs, ng, h->d_SD + kSDW, kSD, c.s));
       HIPCHK(h, hipMemcpyAsync(SD, h->d_SD, (size_t)ng * kSD * 8, hipMemcpyDeviceToHost, c.s));
       HIPCHK(h, hipStreamSynchronize(c.s));
       c.harvest();
-      std::vector<double> hcol((size_t)ng * (j + 1)), hn(ng, 0.0);
+      // true coefficients: h_ij = s_i s_j h~_i, ||w|| = s_j ||W||
+      std::vector<double> hcol((size_t)ng * (j + 1)), wn(ng, 0.0);
       bool reorth = false;
       for (int g = 0; g < ng; ++g) {
         act[g] = 0;
         if (!grp[g].active) continue;
+        const Arnoldi& A_ = grp[g];
         const double* sg = SD + (size_t)g * kSD;
-        for (int i = 0; i <= j; ++i) hcol[(size_t)g * (j + 1) + i] = sg[kSDH + i];
+        for (int i = 0; i <= j; ++i)
+          hcol[(size_t)g * (j + 1) + i] = A_.s[i] * A_.s[j] * sg[kSDH + i];
         const double wn0 = sqrt(sg[kSDH + j + 1]);
-        hn[g] = sqrt(sg[kSDW]);
-        if (hn[g] < 0.1 * wn0) { act[g] = 1; reorth = true; }   // second CGS pass
+        wn[g] = sqrt(sg[kSDW]);
+        if (wn[g] < 0.1 * wn0) { act[g] = 1; reorth = true; }   // second CGS pass
       }
       if (reorth) {
         double rlen = 0.0;
@@ -1125,35 +1170,49 @@ fmp_status fgmres(Ctx& c, const double* b, double* x, double* ws) {
         HIPCHK(h, hipMemcpyAsync(h->d_act, act, (size_t)ng * 4, hipMemcpyHostToDevice, c.s));
         HIPCHK(h, orth_dot(c, G, h->d_act, rlen, V, (long long)vb, j + 1, w));
         HIPCHK(h, launch_reduce_seg(h->d_part, j + 2, G.segs, ng, h->d_SD + kSDH, kSD, c.s));
-        HIPCHK(h, orth_update(c, G, h->d_act, rlen, V, (long long)vb, j + 1, h->d_SD + kSDH, kSD, w));
+        HIPCHK(h, orth_update(c, G, h->d_act, rlen, V, (long long)vb, j + 1, h->d_SD + kSDH,
+                              h->d_SD + kSDS, kSD, w));
         HIPCHK(h, launch_reduce_seg(h->d_part, 1, G.segs, ng, h->d_SD + kSDW, kSD, c.s));
         HIPCHK(h, hipMemcpyAsync(SD, h->d_SD, (size_t)ng * kSD * 8, hipMemcpyDeviceToHost, c.s));
         HIPCHK(h, hipStreamSynchronize(c.s));
         c.harvest();
         for (int g = 0; g < ng; ++g) {
           if (!act[g]) continue;
+          const Arnoldi& A_ = grp[g];
           const double* sg = SD + (size_t)g * kSD;
-          for (int i = 0; i <= j; ++i) hcol[(size_t)g * (j + 1) + i] += sg[kSDH + i];
-          hn[g] = sqrt(sg[kSDW]);
+          for (int i = 0; i <= j; ++i)
+            hcol[(size_t)g * (j + 1) + i] += A_.s[i] * A_.s[j] * sg[kSDH + i];
+          wn[g] = sqrt(sg[kSDW]);
         }
       }
       ++it;
       bool any = false;
+      std::fill(fac.begin(), fac.end(), 1.0);
       for (int g = 0; g < ng; ++g) {
         Arnoldi& A_ = grp[g];
-        if (!A_.active) { h->h_fac[g] = 0.0; act[g] = 0; continue; }
-        if (!isfinite(hn[g])) return FMP_ERR_BREAKDOWN;
-        const double est = A_.add(j, &hcol[(size_t)g * (j + 1)], hn[g]);
+        act[g] = 0;
+        if (!A_.active) continue;
+        const double hn = A_.s[j] * wn[g];
+        if (!isfinite(hn)) return FMP_ERR_BREAKDOWN;
+        const double est = A_.add(j, &hcol[(size_t)g * (j + 1)], hn);
         A_.iters++;
-        if (hn[g] == 0.0 || est <= tol * A_.r0) A_.active = false;
+        if (hn == 0.0 || est <= tol * A_.r0) {
+          A_.active = false;
+          fac[g] = 0.0;
+        }
         any = any || A_.active;
-        h->h_fac[g] = A_.active ? 1.0 / hn[g] : 0.0;
+        A_.s[j + 1] = A_.active ? 1.0 / wn[g] : 0.0;    // v_{j+1} = W / ||W||
+        if (A_.active && (A_.s[j + 1] > 1e15 || A_.s[j + 1] < 1e-15)) {
+          fac[g] = A_.s[j + 1];
+          A_.s[j + 1] = 1.0;
+        }
+        SD[(size_t)g * kSD + kSDS + j + 1] = A_.s[j + 1] * A_.s[j + 1];
         act[g] = A_.active ? 1 : 0;
       }
       if (c.o->capture && it <= c.o->capture_count) {   // x_it = x + Z y (one group)
         Arnoldi& A0 = grp[0];
         A0.solve();
-        for (int i = 0; i < A0.ncols; ++i) SD[kSDY + i] = A0.y[i];
+        for (int i = 0; i < A0.ncols; ++i) SD[kSDY + i] = A0.y[i] * A0.s[i];
         double* slot = c.o->capture + (size_t)(it - 1) * n;
         HIPCHK(h, hipMemcpyAsync(h->d_SD + kSDY, SD + kSDY, A0.ncols * 8, hipMemcpyHostToDevice, c.s));
         HIPCHK(h, hipMemcpyAsync(slot, x, n * 8, hipMemcpyDeviceToDevice, c.s));
@@ -1162,9 +1221,9 @@ fmp_status fgmres(Ctx& c, const double* b, double* x, double* ws) {
       }
       if (!any || it >= c.o->max_iter) break;
       HIPCHK(h, push());
-      HIPCHK(h, launch_scale_seg(w, h->d_fac, w, G.map, c.s));
+      if ((st = fix_scale(w, fac))) return st;
     }
-    // x += Z y per group (y = 0 beyond a group's own column count)
+    // x += Z (y s) per group (0 beyond a group's own column count)
     int ncmax = 0;
     for (int g = 0; g < ng; ++g) {
       Arnoldi& A_ = grp[g];
@@ -1172,7 +1231,7 @@ fmp_status fgmres(Ctx& c, const double* b, double* x, double* ws) {
       for (int i = 0; i < m; ++i) sy[i] = 0.0;
       if (A_.finished || A_.ncols == 0) continue;
       A_.solve();
-      for (int i = 0; i < A_.ncols; ++i) sy[i] = A_.y[i];
+      for (int i = 0; i < A_.ncols; ++i) sy[i] = A_.y[i] * A_.s[i];
       ncmax = std::max(ncmax, A_.ncols);
     }
     if (ncmax > 0) {

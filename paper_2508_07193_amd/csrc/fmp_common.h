@@ -61,6 +61,16 @@ struct StencilTile {
 
 constexpr int kStencilTX = 64, kStencilTY = 4, kStencilZC = 16;
 
+// Workgroups of a launch are dealt to the 8 XCDs round-robin (block b runs on
+// XCD b % 8).  xcd_remap(b, nb) renumbers them so that each XCD works through
+// one contiguous run of work items: neighbouring items (adjacent tiles or
+// boxes, which read shared halo lines) then meet in the same L2.
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+  const int q = nb / 8, r = nb % 8;
+  const int x = b % 8, idx = b / 8;
+  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + idx;
+}
+
 // Fixed reduction geometry: stage 1 uses kRedBlocks blocks of 256 threads.
 constexpr int kRedBlocks = 1024;
 constexpr int kMaxDots = 34;    // CGS: up to restart+1 basis vectors + ||w||^2
@@ -126,10 +136,11 @@ hipError_t launch_reduce(const double* partials, int n, double* out, int post, d
 // Per-segment fixed-order reduction: out[g * ostride + i] for i < n, g < nseg.
 hipError_t launch_reduce_seg(const double* partials, int n, const SegDev* segs, int nseg,
                              double* out, int ostride, hipStream_t s);
-// w -= sum_i h_{g,i} V_i on segment g (h_g = h + grp * hld), partial ||w||^2.
-hipError_t launch_mupdate(const double* V, long long ldv, int nv, const double* h, int hld,
-                          double* w, const SegDev* map, const int* act, double* partials,
-                          hipStream_t s);
+// w -= sum_i h_{g,i} sc_{g,i} V_i on segment g (h_g = h + grp * hld, same
+// stride for sc; sc may be null = 1), partial ||w||^2.
+hipError_t launch_mupdate(const double* V, long long ldv, int nv, const double* h,
+                          const double* sc, int hld, double* w, const SegDev* map, const int* act,
+                          double* partials, hipStream_t s);
 // x += sum_i y_{g,i} Z_i on segment g (y_g = y + grp * yld).
 hipError_t launch_xupdate(const double* Z, long long ldz, int nz, const double* y, int yld,
                           double* x, const SegDev* map, hipStream_t s);
@@ -137,7 +148,8 @@ hipError_t launch_axpby(double a, const double* x, double b, const double* y, do
                         long long len, hipStream_t s);   // out = a x + b y
 hipError_t launch_scale_copy(const double* x, double a, double* out, long long len,
                              hipStream_t s);              // out = a x
-// out = fac[grp] x on each segment (in place allowed).
+// out = fac[grp] x on each segment (in place allowed; in place, segments
+// with factor 1 are skipped).
 hipError_t launch_scale_seg(const double* x, const double* fac, double* out, const SegDev* map,
                             hipStream_t s);
 // r = b - y with every PEC-wall slot set to 0, partial ||r||^2 per block;

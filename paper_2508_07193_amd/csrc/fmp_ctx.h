@@ -87,10 +87,13 @@ struct fmp_ctx {
   };
   bool use_graph = false;
   hipStream_t cap_stream = nullptr;
-  // batches alternate between two private streams and two staging buffers
-  void* d_Wb = nullptr;
-  hipStream_t bat_stream[2] = {nullptr, nullptr};
-  hipEvent_t ev_fork = nullptr, ev_join[2] = {nullptr, nullptr};
+  // batch k runs on private stream k % nstreams with staging buffer k % nstreams
+  static constexpr int kMaxStreams = 2;
+  void* d_Wk[kMaxStreams] = {nullptr, nullptr};
+  int n_wbuf = 1;
+  hipStream_t bat_stream[kMaxStreams] = {nullptr, nullptr};
+  hipEvent_t ev_fork = nullptr;
+  hipEvent_t ev_join[kMaxStreams] = {nullptr, nullptr};
   std::vector<Graph> graphs;
   std::string err;
 };

@@ -120,9 +120,12 @@ __global__ __launch_bounds__(kThreads) void k_mdot(const double* __restrict__ V,
   block_store<NV + 1>(acc, NV + 1, partials);   // <w,w> lands in column NV
 }
 
+// coefficients h_{g,i} * sc_{g,i} (sc = null: 1): the basis may be stored
+// unnormalised, v_i = s_i * V_i, in which case sc_i = s_i^2
 template <int NV>
 __global__ __launch_bounds__(kThreads) void k_mupdate(const double* __restrict__ V, long long ldv,
-                                                      const double* __restrict__ h, int hld,
+                                                      const double* __restrict__ h,
+                                                      const double* __restrict__ sc, int hld,
                                                       double* __restrict__ w,
                                                       const SegDev* __restrict__ map,
                                                       const int* __restrict__ act,
@@ -132,7 +135,7 @@ __global__ __launch_bounds__(kThreads) void k_mupdate(const double* __restrict__
   if (!act || act[sg.grp]) {
     double hh[NV];
 #pragma unroll
-    for (int i = 0; i < NV; ++i) hh[i] = h[sg.grp * hld + i];
+    for (int i = 0; i < NV; ++i) hh[i] = h[sg.grp * hld + i] * (sc ? sc[sg.grp * hld + i] : 1.0);
     dbl2* __restrict__ w2 = reinterpret_cast<dbl2*>(w);
     seg_walk2(
         sg,
@@ -140,7 +143,7 @@ __global__ __launch_bounds__(kThreads) void k_mupdate(const double* __restrict__
           dbl2 we = w2[p];
 #pragma unroll
           for (int i = 0; i < NV; ++i) {
-            const dbl2 v = reinterpret_cast<const dbl2*>(V + i * ldv)[p];
+            const dbl2 v = ld_stream(V + i * ldv, p);
             we.x = __builtin_fma(-hh[i], v.x, we.x);
             we.y = __builtin_fma(-hh[i], v.y, we.y);
           }
@@ -215,6 +218,7 @@ __global__ __launch_bounds__(kThreads) void k_scale_seg(const double* __restrict
                                                         const SegDev* __restrict__ map) {
   const SegDev sg = map[blockIdx.x];
   const double a = fac[sg.grp];
+  if (a == 1.0 && x == out) return;   // in-place scaling by one: nothing to do
   const dbl2* __restrict__ x2 = reinterpret_cast<const dbl2*>(x);
   dbl2* __restrict__ o2 = reinterpret_cast<dbl2*>(out);
   seg_walk2(
@@ -415,13 +419,14 @@ struct NV {
     else
       NV<N - 1>::mdot(nv, V, ldv, w, map, act, part, s);
   }
-  static void mupdate(int nv, const double* V, long long ldv, const double* h, int hld, double* w,
-                      const SegDev* map, const int* act, double* part, hipStream_t s) {
+  static void mupdate(int nv, const double* V, long long ldv, const double* h, const double* sc,
+                      int hld, double* w, const SegDev* map, const int* act, double* part,
+                      hipStream_t s) {
     if (nv == N)
-      hipLaunchKernelGGL((k_mupdate<N>), dim3(kRedBlocks), dim3(kThreads), 0, s, V, ldv, h, hld, w,
-                         map, act, part);
+      hipLaunchKernelGGL((k_mupdate<N>), dim3(kRedBlocks), dim3(kThreads), 0, s, V, ldv, h, sc,
+                         hld, w, map, act, part);
     else
-      NV<N - 1>::mupdate(nv, V, ldv, h, hld, w, map, act, part, s);
+      NV<N - 1>::mupdate(nv, V, ldv, h, sc, hld, w, map, act, part, s);
   }
   static void xupdate(int nz, const double* Z, long long ldz, const double* y, int yld, double* x,
                       const SegDev* map, hipStream_t s) {
@@ -436,8 +441,8 @@ template <>
 struct NV<0> {
   static void mdot(int, const double*, long long, const double*, const SegDev*, const int*,
                    double*, hipStream_t) {}
-  static void mupdate(int, const double*, long long, const double*, int, double*, const SegDev*,
-                      const int*, double*, hipStream_t) {}
+  static void mupdate(int, const double*, long long, const double*, const double*, int, double*,
+                      const SegDev*, const int*, double*, hipStream_t) {}
   static void xupdate(int, const double*, long long, const double*, int, double*, const SegDev*,
                       hipStream_t) {}
 };
@@ -475,12 +480,12 @@ hipError_t launch_reduce_seg(const double* partials, int n, const SegDev* segs, 
   return hipGetLastError();
 }
 
-hipError_t launch_mupdate(const double* V, long long ldv, int nv, const double* h, int hld,
-                          double* w, const SegDev* map, const int* act, double* partials,
-                          hipStream_t s) {
+hipError_t launch_mupdate(const double* V, long long ldv, int nv, const double* h,
+                          const double* sc, int hld, double* w, const SegDev* map, const int* act,
+                          double* partials, hipStream_t s) {
   if (nv < 1 || nv > 33) return hipErrorInvalidValue;
   if (!aligned16(V) || !aligned16(w) || (ldv & 1)) return hipErrorInvalidValue;
-  NV<33>::mupdate(nv, V, ldv, h, hld, w, map, act, partials, s);
+  NV<33>::mupdate(nv, V, ldv, h, sc, hld, w, map, act, partials, s);
   return hipGetLastError();
 }
 

@@ -86,7 +86,7 @@ __global__ __launch_bounds__(256) void k_mpass_a(const double* __restrict__ r, _
   constexpr int MAXE = (ZS * NP * NP + 255) / 256;
   __shared__ float buf[ZS * NP * NP];
   __shared__ float obuf[ZS * NP * NP];
-  const int4 wk = work[blockIdx.x];
+  const int4 wk = work[xcd_remap(blockIdx.x, gridDim.x)];
   const BoxDev& B = boxes[wk.x];
   const int q = wk.y, z0 = wk.z;
   const int nx = B.nx, ny = B.ny, nz = B.nz;
@@ -151,7 +151,7 @@ __global__ __launch_bounds__(256) void k_mpass_b(__bf16* __restrict__ W,
   constexpr int MAXE = (3 * NP * 64 + 255) / 256;
   __shared__ float L[3][NP][64];
   __shared__ float X[3][NP][64];
-  const int4 wk = work[blockIdx.x];
+  const int4 wk = work[xcd_remap(blockIdx.x, gridDim.x)];
   const BoxDev& B = boxes[wk.x];
   const int nx = B.nx, ny = B.ny, nz = B.nz;
   const int plane = ny * nx, c0 = wk.y;
@@ -219,7 +219,7 @@ __global__ __launch_bounds__(256) void k_mpass_c(const __bf16* __restrict__ W, d
   constexpr int MAXE = (ZS * NP * NP + 255) / 256;
   __shared__ float buf[ZS * NP * NP];
   __shared__ float obuf[ZS * NP * NP];
-  const int4 wk = work[blockIdx.x];
+  const int4 wk = work[xcd_remap(blockIdx.x, gridDim.x)];
   const BoxDev& B = boxes[wk.x];
   const int q = wk.y, z0 = wk.z;
   const int nx = B.nx, ny = B.ny, nz = B.nz;

@@ -29,12 +29,6 @@ namespace {
 constexpr int TX = kStencilTX, TY = kStencilTY;
 constexpr int HX = TX + 2, HY = TY + 2;   // tile with halo
 
-__device__ __forceinline__ int xcd_remap(int b, int nb) {
-  const int q = nb / 8, r = nb % 8;
-  const int x = b % 8, idx = b / 8;
-  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + idx;
-}
-
 __global__ __launch_bounds__(TX * TY) void k_curlcurl(const double* __restrict__ x,
                                                       double* __restrict__ y,
                                                       const DomainDev* __restrict__ doms,

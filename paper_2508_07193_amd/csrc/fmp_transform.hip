@@ -176,7 +176,7 @@ __global__ __launch_bounds__(kAC) void k_pass_a(const double* __restrict__ r, T*
   constexpr int MAXE = (ZS * NP * NP + kAC - 1) / kAC;
   constexpr int NH = NP / 2;
   __shared__ T buf[ZS * NP * NP];
-  const int4 wk = work[blockIdx.x];
+  const int4 wk = work[xcd_remap(blockIdx.x, gridDim.x)];
   const BoxDev& B = boxes[wk.x];
   const int q = wk.y, z0 = wk.z;
   const int nx = B.nx, ny = B.ny, nz = B.nz;
@@ -221,13 +221,33 @@ __global__ __launch_bounds__(kAC) void k_pass_a(const double* __restrict__ r, T*
 }
 
 // ---------------------------------------------------------------- pass B
+// The column is held in registers when its length nz is a compile-time
+// constant (nz = NP or NP - 1, which covers every box of a class at the
+// usual sides): the forward butterfly reads the registers and writes the
+// spectral rows to LDS for the solve, and the inverse reads the solved rows
+// back from registers.  Other lengths go through LDS.
+template <typename T, int NP, int NZ, int TZ>
+__device__ __forceinline__ void colz_fwd(const T* __restrict__ tabz, const T (&v)[NP],
+                                         T (*exq)[64], int lane) {
+  fwd_bfly<T, NP / 2>(tabz, half_geom(NZ, TZ), [&](int l) { return v[l]; },
+                      [&](int r, T val) { exq[r][lane] = val; });
+}
+template <typename T, int NP, int NZ, int TZ>
+__device__ __forceinline__ void colz_inv(const T* __restrict__ tabz, const T (&e)[NP], T* col,
+                                         int plane, bool active) {
+  inv_bfly<T, NP / 2>(tabz, half_geom(NZ, TZ), [&](int r) { return e[r]; },
+                      [&](int l, T val) {
+                        if (active) col[(long long)l * plane] = val;
+                      });
+}
+
 template <typename T, int NP>
 __global__ __launch_bounds__(192) void k_pass_b(T* __restrict__ W, const BoxDev* __restrict__ boxes,
                                                 const int4* __restrict__ work,
                                                 const T* __restrict__ tab) {
   constexpr int NH = NP / 2;
   __shared__ T ex[3][NP][64];
-  const int4 wk = work[blockIdx.x];
+  const int4 wk = work[xcd_remap(blockIdx.x, gridDim.x)];
   const BoxDev& B = boxes[wk.x];
   // one wave per component; readfirstlane tells the compiler q is wave-uniform,
   // so the table entries below stay scalar operands
@@ -238,17 +258,27 @@ __global__ __launch_bounds__(192) void k_pass_b(T* __restrict__ W, const BoxDev*
   const int c = wk.y + lane;
   const bool active = c < plane;
   T* col = W + B.w_off + (long long)q * B.vol + (active ? c : 0);
+  const int tz = q == 2 ? 0 : 1;                  // DCT-II along z for E_z, DST-I otherwise
+  const T* tabz = tab + B.half[2][tz];
+  // 0: nz = NP, 1: nz = NP - 1, 2: other (through LDS); uniform over the block
+  const int form = nz == NP ? 0 : (nz == NP - 1 ? 1 : 2);
 
   T v[NP];                                        // the column, all loads in flight
 #pragma unroll
   for (int l = 0; l < NP; ++l) v[l] = col[(long long)min(l, nz - 1) * plane];
+  if (form == 0) {
+    if (tz == 0) colz_fwd<T, NP, NP, 0>(tabz, v, ex[q], lane);
+    else colz_fwd<T, NP, NP, 1>(tabz, v, ex[q], lane);
+  } else if (form == 1) {
+    if (tz == 0) colz_fwd<T, NP, NP - 1, 0>(tabz, v, ex[q], lane);
+    else colz_fwd<T, NP, NP - 1, 1>(tabz, v, ex[q], lane);
+  } else {
 #pragma unroll
-  for (int l = 0; l < NP; ++l) ex[q][l][lane] = v[l];
-  const int tz = q == 2 ? 0 : 1;                  // DCT-II along z for E_z, DST-I otherwise
-  const T* tabz = tab + B.half[2][tz];
-  const Half gz = half_geom(nz, tz);
-  fwd_bfly<T, NH>(tabz, gz, [&](int l) { return ex[q][l][lane]; },
-                  [&](int r, T val) { ex[q][r][lane] = val; });
+    for (int l = 0; l < NP; ++l) ex[q][l][lane] = v[l];
+    const Half gz = half_geom(nz, tz);
+    fwd_bfly<T, NH>(tabz, gz, [&](int l) { return ex[q][l][lane]; },
+                    [&](int r, T val) { ex[q][r][lane] = val; });
+  }
   __syncthreads();
 
   const int yy = active ? c / nx : 0;
@@ -267,13 +297,21 @@ __global__ __launch_bounds__(192) void k_pass_b(T* __restrict__ W, const BoxDev*
     const T rq = q == 0 ? a : (q == 1 ? b : d);
     v[rr] = fmaT<T>(alpha * sq, dot, rq) * recip<T>(fmaT<T>(alpha, fmaT<T>(s3, s3, sxy2), T(1)));
   }
-  __syncthreads();                                // every wave has read all three components
+  if (form == 0) {
+    if (tz == 0) colz_inv<T, NP, NP, 0>(tabz, v, col, plane, active);
+    else colz_inv<T, NP, NP, 1>(tabz, v, col, plane, active);
+  } else if (form == 1) {
+    if (tz == 0) colz_inv<T, NP, NP - 1, 0>(tabz, v, col, plane, active);
+    else colz_inv<T, NP, NP - 1, 1>(tabz, v, col, plane, active);
+  } else {
+    __syncthreads();                              // every wave has read all three components
 #pragma unroll
-  for (int rr = 0; rr < NP; ++rr) ex[q][rr][lane] = v[rr];
-  inv_bfly<T, NH>(tabz, gz, [&](int r) { return ex[q][r][lane]; },
-                  [&](int l, T val) {
-                    if (active) col[(long long)l * plane] = val;
-                  });
+    for (int rr = 0; rr < NP; ++rr) ex[q][rr][lane] = v[rr];
+    inv_bfly<T, NH>(tabz, half_geom(nz, tz), [&](int r) { return ex[q][r][lane]; },
+                    [&](int l, T val) {
+                      if (active) col[(long long)l * plane] = val;
+                    });
+  }
 }
 
 // ---------------------------------------------------------------- pass C
@@ -288,7 +326,7 @@ __global__ __launch_bounds__(kAC) void k_pass_c(const T* __restrict__ W, double*
   constexpr int MAXE = (ZS * NP * NP + kAC - 1) / kAC;
   constexpr int NH = NP / 2;
   __shared__ T buf[ZS * NP * NP];
-  const int4 wk = work[blockIdx.x];
+  const int4 wk = work[xcd_remap(blockIdx.x, gridDim.x)];
   const BoxDev& B = boxes[wk.x];
   const int q = wk.y, z0 = wk.z;
   const int nx = B.nx, ny = B.ny, nz = B.nz;

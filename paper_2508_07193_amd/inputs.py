@@ -93,6 +93,23 @@ def extra_rhs(nx, ny, nz, seed):
     return normal_rhs(np.random.default_rng(seed), nx, ny, nz)
 
 
+def extra_rhs_device(nx, ny, nz, seed, device):
+    """N(0,1) on every unknown slot, zeros on walls, drawn on the device by
+    torch's generator for `device` seeded with `seed` (fast draws of many
+    training right-hand sides; a different stream from extra_rhs)."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    v = torch.randn((3, nz, ny, nx), generator=g, dtype=torch.float64, device=device)
+    v[0, 0, :, :] = 0.0
+    v[0, :, 0, :] = 0.0
+    v[1, 0, :, :] = 0.0
+    v[1, :, :, 0] = 0.0
+    v[2, :, 0, :] = 0.0
+    v[2, :, :, 0] = 0.0
+    return v.reshape(-1)
+
+
 def make_batch_c4(seed=4, n_domains=64, sides=SIDES_C4, c_range=(0.5, 8.0)):
     """64 independent cubic domains: sides uniform over `sides`, c ~ U[0.5, 8], eps = 1.
 

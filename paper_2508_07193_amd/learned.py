@@ -51,7 +51,7 @@ def generate_pairs(h, dims, n_rhs, per_rhs, seed0, rtol_star=1e-11, log=None):
     row = 0
     t0 = time.perf_counter()
     for s in range(n_rhs):
-        b = torch.from_numpy(inputs.extra_rhs(nx, ny, nz, seed0 + s).ravel()).to(dev)
+        b = inputs.extra_rhs_device(nx, ny, nz, seed0 + s, dev)
         xs.zero_()
         h.solve(b, xs, solver="fgmres", rtol=rtol_star, max_iter=400)
         x = h.new_vector()

@@ -126,7 +126,8 @@ def test_garbage_model_falls_back_and_converges():
     x = h.new_vector()
     info = h.solve(b, x, solver="fgmres", rtol=1e-8, max_iter=300)
     assert info["status"] == "FMP_OK" and info["rel_residual_true"] <= 1e-8
-    assert info["used_fallback"] >= 1
+    # every step is rejected; after three in a row the solve drops the model
+    assert info["used_fallback"] == 3
     assert info["iterations"] <= plain["iterations"] + 1
 
 

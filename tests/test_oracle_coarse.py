@@ -62,3 +62,35 @@ def test_bf16_rounding_matches_torch():
     x = np.random.default_rng(3).standard_normal(10000).astype(np.float32) * 7
     ref = torch.from_numpy(x).to(torch.bfloat16).to(torch.float64).numpy()
     assert np.array_equal(coarse.bf16_round(x), ref)
+
+
+@pytest.mark.slow
+def test_ideal_coarse_correction_bounds_the_learned_gain():
+    """Upper bound on what any coarse correction through P0 can gain.
+
+    The learned part adds P0 MLP(R0 r) to the RAS step; the best any network
+    can do is the exact restricted remaining error, z = M r + P0 R0 (A^-1 r -
+    M r).  On a 24^3 grid with 8^3 subdomains and c = 8 this ideal correction
+    saves FGMRES iterations when eps = 1, but not when eps_r varies U[1,10]
+    on 4^3-cell cubes inside each subdomain: there the RAS error is the
+    constant-coefficient box solve's mismatch inside the subdomains, which
+    piecewise-constant coarse functions do not capture.
+    """
+    import scipy.sparse.linalg as spla
+    from oracle import krylov, ras, yee
+    n, sub, c = 24, (8, 8, 8), 8.0
+    out = {}
+    for name, blk in (("uniform", 0), ("contrast", 4)):
+        P = inputs.make_problem(dict(n=n, sub=8, c=c, eps_block=blk, seed=3))
+        eps_cell = yee.expand_eps(P["eps"], blk, n, n, n) if blk else None
+        A = yee.assemble_A(n, n, n, c, eps_cell).tocsc()
+        lu = spla.splu(A)
+        Af = lambda v: yee.to_padded(A @ yee.from_padded(v), n, n, n)
+        Mf = lambda v: ras.ras_apply(v, c, sub, 1, eps_cell)
+        Ainv = lambda v: yee.to_padded(lu.solve(yee.from_padded(v)), n, n, n)
+        ideal = lambda v: Mf(v) + coarse.prolong(coarse.restrict(Ainv(v) - Mf(v), sub), v.shape, sub)
+        _, ip = krylov.fgmres(Af, P["rhs"], M=Mf, tol=1e-8, restart=30)
+        _, ii = krylov.fgmres(Af, P["rhs"], M=ideal, tol=1e-8, restart=30)
+        out[name] = (ip["iterations"], ii["iterations"])
+    assert out["uniform"][1] <= out["uniform"][0] - 2, out
+    assert out["contrast"][1] >= out["contrast"][0] - 1, out
