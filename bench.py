@@ -26,20 +26,24 @@ HBM_PEAK_GBS = 8000.0
 
 # HBM traffic of each roofline kernel as a multiple of its algorithmic bytes,
 # from rocprofv3 FETCH_SIZE / WRITE_SIZE runs of this bench on the 256^3
-# workload (KiB per dispatch, scaled by a plain in-place scale of one vector:
-# FETCH x2.000, WRITE x1.000).  A ratio holds only for the kernel sources it
-# was measured on: if any listed source changed since, traffic is null.
+# workload (KiB per dispatch, scaled by what the counters read for a plain
+# device copy of one vector: FETCH x2.000, WRITE x1.000).  A ratio holds only
+# for the kernel sources it was measured on: if any listed source changed
+# since, traffic is null.
 TRAFFIC = {
-    "k_mupdate": (1.0000, {"fmp_krylov.hip": "b605955e21ab53cd3a1b2791b328b879484d8b111c435f98e7516558b66cb171"}),
-    "k_mdot": (1.0000, {"fmp_krylov.hip": "b605955e21ab53cd3a1b2791b328b879484d8b111c435f98e7516558b66cb171"}),
-    "k_curlcurl": (1.0729, {"fmp_stencil.hip": "1513c873efb6702a2f91e867f0820d685c6e24d499270475f779a056e79f98e2"}),
-    "precond_apply": (4.100, {"fmp_transform.hip": "1488a8003c092fe35ca78da18e8ef8ea34e31f43e3be4d6032ace881387999b7",
-                              "fmp_api.hip": "0e0e3233cd16aa25024f2a2da0f91e17b4f2c44547aff657dacbea0e7fe3ccdb"}),
+    "k_mupdate": (1.0000, {"fmp_krylov.hip": "f1f24bd32b8cc02cdd320efeebc215ced08006197fdf91b76559306a267737d5",
+                          "fmp_common.h": "0150c906c8e7097f7526eb2705dbd6e634fed83d49309e950b57f50d8ba7bb17"}),
+    "k_mdot": (1.0000, {"fmp_krylov.hip": "f1f24bd32b8cc02cdd320efeebc215ced08006197fdf91b76559306a267737d5",
+                          "fmp_common.h": "0150c906c8e7097f7526eb2705dbd6e634fed83d49309e950b57f50d8ba7bb17"}),
+    "k_curlcurl": (1.0720, {"fmp_stencil.hip": "de1405a66a1406a29665d8febfe02f57f73061b26dfc1278dde215ed059136fb",
+                          "fmp_common.h": "0150c906c8e7097f7526eb2705dbd6e634fed83d49309e950b57f50d8ba7bb17"}),
 }
 
 
 def traffic_ratio(name):
     import hashlib
+    if name not in TRAFFIC:
+        return None
     ratio, srcs = TRAFFIC[name]
     d = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2508_07193_amd", "csrc")
     for f, h in srcs.items():

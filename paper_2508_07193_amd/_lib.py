@@ -68,6 +68,7 @@ def load():
     L.fmp_vector_layout.argtypes = [vp, C.POINTER(C.c_int64)]
     L.fmp_curlcurl_apply.argtypes = [vp, vp, vp, vp]
     L.fmp_apply_precond.argtypes = [vp, vp, vp, vp]
+    L.fmp_autotune.argtypes = [vp, vp, vp, C.POINTER(TuneEntry), i32, C.POINTER(i32), vp]
     L.fmp_solve_workspace.argtypes = [vp, C.POINTER(SolveOpts), C.POINTER(sz)]
     L.fmp_solve.argtypes = [vp, vp, vp, C.POINTER(SolveOpts), vp, sz, C.POINTER(SolveInfo), vp]
     L.fmp_coarse_size.argtypes = [vp, C.POINTER(i32)]

@@ -295,7 +295,7 @@ def test_full_256_sampled_stencil_and_precond():
     got = np.array([yo[p] for p in pts])
     assert np.abs(got - ref).max() <= 1e-13 * np.abs(P["rhs"]).max()
     # corner, edge, face and interior subdomains (index = (sz*8 + sy)*8 + sx)
-    which = [0, 7, 63, 511, 8 * 64 + 3 * 8 + 4, 3 * 64 + 4 * 8 + 5]
+    which = [0, 7, 63, 511, 4 * 64 + 3 * 8 + 4, 3 * 64 + 4 * 8 + 5]
     blocks = ras.ras_apply_subset(P["rhs"], P["c"], P["sub"], 1, eps_cell, which)
     for idx, (own, blk) in blocks.items():
         (x0, x1), (y0, y1), (z0, z1) = own
