@@ -182,7 +182,7 @@ def batch_leg(args, dev, log):
     z = h.new_vector()
     tune = h.autotune(b, z)
     chosen = [t for t in tune if t["chosen"]][0]
-    log(f"[batch] autotune: {[(t['batch_boxes'], t['streams'], round(t['apply_ms'], 3)) for t in tune]}")
+    log(f"[batch] autotune: {[(t['batch_boxes'], t['streams'], t['slab_order'], round(t['apply_ms'], 3)) for t in tune]}")
     h.apply_precond(b, z)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -228,9 +228,10 @@ def batch_leg(args, dev, log):
                                          iterations=info_c["iterations"],
                                          max_domain_rel_residual=max(rel_c)),
                 precond_applies_per_s=round(1e3 / t_pre, 1), precond_ms=round(t_pre, 4),
-                autotune=dict(chosen=dict(batch_boxes=chosen["batch_boxes"], streams=chosen["streams"]),
-                              candidates=[[t["batch_boxes"], t["streams"], round(t["apply_ms"], 4)]
-                                          for t in tune]),
+                autotune=dict(chosen=dict(batch_boxes=chosen["batch_boxes"], streams=chosen["streams"],
+                                          slab_order=chosen["slab_order"]),
+                              candidates=[[t["batch_boxes"], t["streams"], t["slab_order"],
+                                           round(t["apply_ms"], 4)] for t in tune]),
                 launch="hipGraph replay of the per-class, per-batch pass sequence")
 
 
@@ -300,8 +301,9 @@ def main():
                         use_graph=True)
         t = hh.autotune(b)
         c = [e for e in t if e["chosen"]][0]
-        log(f"[{prec}] autotune: {[(e['batch_boxes'], e['streams'], round(e['apply_ms'], 4)) for e in t]}")
-        return hh, dict(batch_boxes=c["batch_boxes"], streams=c["streams"], graph=True)
+        log(f"[{prec}] autotune: {[(e['batch_boxes'], e['streams'], e['slab_order'], round(e['apply_ms'], 4)) for e in t]}")
+        return hh, dict(batch_boxes=c["batch_boxes"], streams=c["streams"], slab_order=c["slab_order"],
+                        graph=True)
 
     # ---------------- plain FP64 FlashMP
     h, plan64 = tuned_handle("fp64")

@@ -184,14 +184,16 @@ typedef struct {
   int32_t batch_boxes;   /* boxes per batch (staging reused batch after batch)  */
   int32_t streams;       /* 1: batches in order; 2: consecutive batches on two
                             private streams with two staging buffers (overlap) */
+  int32_t slab_order;    /* gather/scatter work order: 0 box by box, 1 slab by
+                            slab across the batch's boxes (shared halo lines)  */
   double apply_ms;       /* mean preconditioner apply time (HIP events)         */
   int32_t chosen;        /* 1 for the candidate the handle now uses             */
 } fmp_tune_entry;
 
 /* Autotuner of the preconditioner's launch plan: times fmp_apply_precond(r, z)
  * (three applies after a warm-up, or graph replays when use_graph is set) for
- * every candidate batch size (16 .. 1024 boxes and all boxes, per size class)
- * and stream count, and keeps the fastest plan in the handle.  Every plan
+ * every candidate batch size (16 .. 1024 boxes and all boxes, per size class),
+ * stream count and gather work order, and keeps the fastest plan.  Every plan
  * computes the same z bit for bit; only the schedule changes.  Requires a
  * handle set up with batch_boxes = -1 (else FMP_ERR_UNSUPPORTED).  r, z:
  * device vectors (not overlapping); z is overwritten.  entries: optional host

@@ -63,10 +63,17 @@ int class_of(int n) {
 }
 
 // Cut the class-ordered boxes into batches of at most `batch` boxes of one
-// class; assign each box its staging offset inside its batch.  Returns the
+// class; assign each box its staging offset inside its batch.  Pass A / C
+// work items (box, component, first plane of a z-slab) are ordered per batch
+// either box by box (h->slab_order = 0) or by component, then slab, then box
+// (1): then neighbouring boxes (x fastest, then y) gather the same slab at
+// the same time, so the cache lines they share (the overlap rows, and the
+// partial lines at both ends of every 34-cell row) are fetched once into the
+// XCD's L2, at the price of more distinct pages in flight.  Returns the
 // largest batch's staging size (elements).
 long long plan_batches(fmp_ctx* h, int batch) {
   h->launches.clear();
+  h->work_a.clear();
   h->batch = batch;
   long long wmax = 0;
   const auto cls_at = [&](size_t i) {
@@ -78,15 +85,32 @@ long long plan_batches(fmp_ctx* h, int batch) {
     size_t i1 = i0;
     while (i1 < h->order.size() && cls_at(i1) == c && (int)(i1 - i0) < batch) ++i1;
     long long woff = 0;
+    int nzmax = 0;
     for (size_t i = i0; i < i1; ++i) {
       BoxDev& B = h->boxes[h->order[i]];
       B.w_off = woff;                 // staging is reused batch after batch
       woff += 3 * B.vol;
+      nzmax = std::max(nzmax, B.nz);
     }
     wmax = std::max(wmax, woff);
-    if (c >= 0)
-      h->launches.push_back(Launch{c, h->wa0[i0], h->wa0[i1] - h->wa0[i0], h->wb0[i0],
+    const int a0 = (int)h->work_a.size();
+    if (c >= 0) {
+      const int zs = (h->prec == FMP_BF16) ? mfma_zslab(c) : pass_a_zslab(c);
+      if (h->slab_order) {
+        for (int q = 0; q < 3; ++q)
+          for (int z0 = 0; z0 < nzmax; z0 += zs)
+            for (size_t i = i0; i < i1; ++i)
+              if (z0 < h->boxes[h->order[i]].nz)
+                h->work_a.push_back(make_int4(h->order[i], q, z0, 0));
+      } else {
+        for (size_t i = i0; i < i1; ++i)
+          for (int q = 0; q < 3; ++q)
+            for (int z0 = 0; z0 < h->boxes[h->order[i]].nz; z0 += zs)
+              h->work_a.push_back(make_int4(h->order[i], q, z0, 0));
+      }
+      h->launches.push_back(Launch{c, a0, (int)h->work_a.size() - a0, h->wb0[i0],
                                    h->wb0[i1] - h->wb0[i0]});
+    }
     i0 = i1;
   }
   return wmax;
@@ -471,19 +495,14 @@ fmp_status fmp_setup_subdomains(const fmp_domain_desc* domains, int32_t n_domain
   h->order.resize(h->boxes.size());
   for (size_t i = 0; i < h->order.size(); ++i) h->order[i] = (int)i;
   std::stable_sort(h->order.begin(), h->order.end(), [&](int a, int b) { return cls[a] < cls[b]; });
-  std::vector<int4> work_a, work_b;
+  std::vector<int4> work_b;
   for (size_t i = 0; i < h->order.size(); ++i) {
     const int bi = h->order[i];
     const BoxDev& B = h->boxes[bi];
-    h->wa0.push_back((int)work_a.size());
     h->wb0.push_back((int)work_b.size());
     if (cls[bi] < 0) continue;
-    const int zs = (h->prec == FMP_BF16) ? mfma_zslab(cls[bi]) : pass_a_zslab(cls[bi]);
-    for (int q = 0; q < 3; ++q)
-      for (int z0 = 0; z0 < B.nz; z0 += zs) work_a.push_back(make_int4(bi, q, z0, 0));
     for (int c0 = 0; c0 < B.nx * B.ny; c0 += 64) work_b.push_back(make_int4(bi, c0, 0, 0));
   }
-  h->wa0.push_back((int)work_a.size());
   h->wb0.push_back((int)work_b.size());
   // batch = -1: keep room for every candidate of fmp_autotune (whole classes)
   h->tunable = pd->batch_boxes < 0;
@@ -514,7 +533,7 @@ fmp_status fmp_setup_subdomains(const fmp_domain_desc* domains, int32_t n_domain
   const size_t tab_bytes = (h->prec == FMP_BF16) ? tab16.size() * 2 : tab64.size() * tsz;
   const size_t o_tab = cur; cur = align_up(cur + std::max<size_t>(tab_bytes, 1));
   const size_t o_sig32 = cur; cur = align_up(cur + std::max<size_t>(tab64.size() * 4, 1));
-  const size_t o_wa = cur; cur = align_up(cur + work_a.size() * sizeof(int4));
+  const size_t o_wa = cur; cur = align_up(cur + std::max<size_t>(h->work_a.size(), 1) * sizeof(int4));
   const size_t o_wb = cur; cur = align_up(cur + work_b.size() * sizeof(int4));
   const size_t o_part = cur; cur = align_up(cur + (size_t)kMaxDots * kRedBlocks * 8);
   const size_t o_S = cur; cur = align_up(cur + kScal * 8);
@@ -583,7 +602,7 @@ fmp_status fmp_setup_subdomains(const fmp_domain_desc* domains, int32_t n_domain
     HIPCHK(hp, hipMemcpyAsync(h->d_tab, tabbytes.data(), tabbytes.size(), hipMemcpyHostToDevice, s));
   if (!sig32.empty())
     HIPCHK(hp, hipMemcpyAsync(h->d_sig32, sig32.data(), sig32.size() * 4, hipMemcpyHostToDevice, s));
-  HIPCHK(hp, hipMemcpyAsync(h->d_work_a, work_a.data(), work_a.size() * sizeof(int4),
+  HIPCHK(hp, hipMemcpyAsync(h->d_work_a, h->work_a.data(), h->work_a.size() * sizeof(int4),
                             hipMemcpyHostToDevice, s));
   HIPCHK(hp, hipMemcpyAsync(h->d_work_b, work_b.data(), work_b.size() * sizeof(int4),
                             hipMemcpyHostToDevice, s));
@@ -662,28 +681,31 @@ fmp_status fmp_autotune(fmp_handle h, const double* r, double* z, fmp_tune_entry
   for (int b : {16, 32, 64, 128, 256, 512, 1024})
     if (b < nbox) batches.push_back(b);
   batches.push_back(nbox);
-  struct Cand { int batch, ns; double ms; };
+  struct Cand { int batch, ns, slab; double ms; };
   std::vector<Cand> cands;
   for (int b : batches)
     for (int ns = 1; ns <= std::min(h->n_wbuf, fmp_ctx::kMaxStreams); ++ns)
-      cands.push_back({b, ns, 0.0});
+      for (int so = 0; so < 2; ++so) cands.push_back({b, ns, so, 0.0});
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIPCHK(h, hipEventCreate(&e0));
   HIPCHK(h, hipEventCreate(&e1));
   const double* coarse = nullptr;   // the learned part does not depend on the plan
-  auto use = [&](int b, int ns) -> fmp_status {
+  auto use = [&](int b, int ns, int so) -> fmp_status {
     for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.exec);
     h->graphs.clear();
+    h->slab_order = so;
     plan_batches(h, b);
     h->nstreams = ns;
     HIPCHK(h, hipMemcpyAsync(h->d_boxes, h->boxes.data(), h->boxes.size() * sizeof(BoxDev),
+                             hipMemcpyHostToDevice, s));
+    HIPCHK(h, hipMemcpyAsync(h->d_work_a, h->work_a.data(), h->work_a.size() * sizeof(int4),
                              hipMemcpyHostToDevice, s));
     HIPCHK(h, hipStreamSynchronize(s));
     return FMP_OK;
   };
   fmp_status st = FMP_OK;
   for (Cand& c : cands) {
-    if ((st = use(c.batch, c.ns)) != FMP_OK) break;
+    if ((st = use(c.batch, c.ns, c.slab)) != FMP_OK) break;
     if (c.ns > 1 && (int)h->launches.size() < c.ns) { c.ms = -1.0; continue; }   // no more overlap
     if ((st = precond_apply(h, r, z, s, coarse)) != FMP_OK) break;      // capture / warm up
     HIPCHK(h, hipEventRecord(e0, s));
@@ -702,11 +724,12 @@ fmp_status fmp_autotune(fmp_handle h, const double* r, double* z, fmp_tune_entry
   const Cand* best = nullptr;
   for (const Cand& c : cands)
     if (c.ms >= 0.0 && (!best || c.ms < best->ms)) best = &c;
-  if ((st = use(best->batch, best->ns)) != FMP_OK) return st;
+  if ((st = use(best->batch, best->ns, best->slab)) != FMP_OK) return st;
   int k = 0;
   for (const Cand& c : cands) {
     if (c.ms < 0.0) continue;
-    if (entries && k < max_entries) entries[k] = fmp_tune_entry{c.batch, c.ns, c.ms, &c == best};
+    if (entries && k < max_entries)
+      entries[k] = fmp_tune_entry{c.batch, c.ns, c.slab, c.ms, &c == best};
     ++k;
   }
   if (n_entries) *n_entries = std::min(k, max_entries);

@@ -21,13 +21,15 @@ struct fmp_ctx {
   std::vector<BoxDev> boxes;
   std::vector<long long> offsets;
   std::vector<Launch> launches;
-  // batch planning: boxes in class order, their first pass-A / pass-B work
-  // items (one extra entry at the end), the staging capacity per W buffer
+  // batch planning: boxes in class order, each box's first pass-B work item
+  // (one extra entry at the end), the staging capacity per W buffer
   // (elements) and the current plan's knobs
-  std::vector<int> order, wa0, wb0;
+  std::vector<int> order, wb0;
+  std::vector<int4> work_a;    // pass A / C items of the current plan (see plan_batches)
   long long w_cap = 0;
   int batch = 0;               // boxes per batch
   int nstreams = 2;            // 1 = batches in order on the caller's stream
+  int slab_order = 1;          // pass A / C items: 1 = slab-major, 0 = box-major
   bool tunable = false;
   int prec = 0;
   int overlap = 1;

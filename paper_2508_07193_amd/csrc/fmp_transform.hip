@@ -77,9 +77,67 @@ __device__ __forceinline__ T row_dot(const T* __restrict__ row, const T (&v)[NH]
   return a0 + a1;
 }
 
+// two rows at once: four independent FMA chains instead of two, with each
+// output summed in the same order as row_dot (results are identical)
+template <typename T, int NH>
+__device__ __forceinline__ void row_dot2(const T* __restrict__ r0, const T* __restrict__ r1,
+                                         const T (&v)[NH], T& o0, T& o1) {
+  T a0 = T(0), a1 = T(0), b0 = T(0), b1 = T(0);
+#pragma unroll
+  for (int j = 0; j + 1 < NH; j += 2) {
+    a0 = fmaT<T>(r0[j], v[j], a0);
+    b0 = fmaT<T>(r1[j], v[j], b0);
+    a1 = fmaT<T>(r0[j + 1], v[j + 1], a1);
+    b1 = fmaT<T>(r1[j + 1], v[j + 1], b1);
+  }
+  if (NH & 1) {
+    a0 = fmaT<T>(r0[NH - 1], v[NH - 1], a0);
+    b0 = fmaT<T>(r1[NH - 1], v[NH - 1], b0);
+  }
+  o0 = a0 + a1;
+  o1 = b0 + b1;
+}
+
+// one row of each of two tables times its own vector (the inverse's even and
+// odd parts), four chains
+template <typename T, int NH>
+__device__ __forceinline__ void row_dot2(const T* __restrict__ r0, const T* __restrict__ r1,
+                                         const T (&v0)[NH], const T (&v1)[NH], T& o0, T& o1) {
+  T a0 = T(0), a1 = T(0), b0 = T(0), b1 = T(0);
+#pragma unroll
+  for (int j = 0; j + 1 < NH; j += 2) {
+    a0 = fmaT<T>(r0[j], v0[j], a0);
+    b0 = fmaT<T>(r1[j], v1[j], b0);
+    a1 = fmaT<T>(r0[j + 1], v0[j + 1], a1);
+    b1 = fmaT<T>(r1[j + 1], v1[j + 1], b1);
+  }
+  if (NH & 1) {
+    a0 = fmaT<T>(r0[NH - 1], v0[NH - 1], a0);
+    b0 = fmaT<T>(r1[NH - 1], v1[NH - 1], b0);
+  }
+  o0 = a0 + a1;
+  o1 = b0 + b1;
+}
+
+// rows k0 .. k0+cnt-1 of a half table times v, two rows per step; the loop
+// stays rolled so that two table rows at a time sit in SGPRs
+template <typename T, int NH, class Out>
+__device__ __forceinline__ void rows_times(const T* __restrict__ M, int cnt, const T (&v)[NH],
+                                           Out out) {
+#pragma unroll 1
+  for (int k = 0; k + 1 < cnt; k += 2) {
+    T o0, o1;
+    row_dot2<T, NH>(M + k * kHS, M + (k + 1) * kHS, v, o0, o1);
+    out(k, o0);
+    out(k + 1, o1);
+  }
+  if (cnt & 1) out(cnt - 1, row_dot<T, NH>(M + (cnt - 1) * kHS, v));
+}
+
 // forward: y = T x; x read through ld(index), y written through st(index, value).
-// Output loops stay rolled so one table row at a time sits in SGPRs.
-template <typename T, int NH, class Load, class Store>
+// TWO = false computes one output at a time (fewer registers: used where the
+// caller already holds a whole pencil and register pressure sets occupancy).
+template <typename T, int NH, bool TWO = true, class Load, class Store>
 __device__ __forceinline__ void fwd_bfly(const T* __restrict__ tab, const Half g, Load ld,
                                          Store st) {
   T sv[NH], dv[NH];
@@ -98,15 +156,20 @@ __device__ __forceinline__ void fwd_bfly(const T* __restrict__ tab, const Half g
   const T* __restrict__ TS = tab;
   const T* __restrict__ TD = tab + kHS * kHS;
   const int NS = g.P + g.mid;
+  if (TWO) {
+    rows_times<T, NH>(TS, NS, sv, [&](int k, T val) { st(g.base + 2 * k, val); });
+    rows_times<T, NH>(TD, g.P, dv, [&](int k, T val) { st(g.base + 2 * k + 1, val); });
+  } else {
 #pragma unroll 1
-  for (int k = 0; k < NS; ++k) st(g.base + 2 * k, row_dot<T, NH>(TS + k * kHS, sv));
+    for (int k = 0; k < NS; ++k) st(g.base + 2 * k, row_dot<T, NH>(TS + k * kHS, sv));
 #pragma unroll 1
-  for (int k = 0; k < g.P; ++k) st(g.base + 2 * k + 1, row_dot<T, NH>(TD + k * kHS, dv));
+    for (int k = 0; k < g.P; ++k) st(g.base + 2 * k + 1, row_dot<T, NH>(TD + k * kHS, dv));
+  }
   if (g.base) st(0, T(0));                        // DST-I: slot 0 holds no mode
 }
 
 // inverse: x = T^T y
-template <typename T, int NH, class Load, class Store>
+template <typename T, int NH, bool TWO = true, class Load, class Store>
 __device__ __forceinline__ void inv_bfly(const T* __restrict__ tab, const Half g, Load ld,
                                          Store st) {
   T ys[NH], yd[NH];
@@ -119,9 +182,14 @@ __device__ __forceinline__ void inv_bfly(const T* __restrict__ tab, const Half g
   const T* __restrict__ TSt = tab + 2 * kHS * kHS;
   const T* __restrict__ TDt = tab + 3 * kHS * kHS;
 #pragma unroll 1
-  for (int j = 0; j < g.P; ++j) {
-    const T e = row_dot<T, NH>(TSt + j * kHS, ys);
-    const T o = row_dot<T, NH>(TDt + j * kHS, yd);
+  for (int j = 0; j < g.P; ++j) {                 // even and odd parts
+    T e, o;
+    if (TWO) {
+      row_dot2<T, NH>(TSt + j * kHS, TDt + j * kHS, ys, yd, e, o);
+    } else {
+      e = row_dot<T, NH>(TSt + j * kHS, ys);
+      o = row_dot<T, NH>(TDt + j * kHS, yd);
+    }
     st(g.base + j, e + o);
     st(g.n - 1 - j, e - o);
   }
@@ -221,6 +289,12 @@ __global__ __launch_bounds__(kAC) void k_pass_a(const double* __restrict__ r, T*
 }
 
 // ---------------------------------------------------------------- pass B
+// FP64 pass B holds a 34-long column per lane; computing two contraction rows
+// at a time there costs an occupancy step (3 -> 2 waves per SIMD), so it
+// takes one row at a time; FP32 has the registers to spare.
+template <typename T>
+constexpr bool kPassBTwo = sizeof(T) == 4;
+
 // The column is held in registers when its length nz is a compile-time
 // constant (nz = NP or NP - 1, which covers every box of a class at the
 // usual sides): the forward butterfly reads the registers and writes the
@@ -229,16 +303,16 @@ __global__ __launch_bounds__(kAC) void k_pass_a(const double* __restrict__ r, T*
 template <typename T, int NP, int NZ, int TZ>
 __device__ __forceinline__ void colz_fwd(const T* __restrict__ tabz, const T (&v)[NP],
                                          T (*exq)[64], int lane) {
-  fwd_bfly<T, NP / 2>(tabz, half_geom(NZ, TZ), [&](int l) { return v[l]; },
-                      [&](int r, T val) { exq[r][lane] = val; });
+  fwd_bfly<T, NP / 2, kPassBTwo<T>>(tabz, half_geom(NZ, TZ), [&](int l) { return v[l]; },
+                                     [&](int r, T val) { exq[r][lane] = val; });
 }
 template <typename T, int NP, int NZ, int TZ>
 __device__ __forceinline__ void colz_inv(const T* __restrict__ tabz, const T (&e)[NP], T* col,
                                          int plane, bool active) {
-  inv_bfly<T, NP / 2>(tabz, half_geom(NZ, TZ), [&](int r) { return e[r]; },
-                      [&](int l, T val) {
-                        if (active) col[(long long)l * plane] = val;
-                      });
+  inv_bfly<T, NP / 2, kPassBTwo<T>>(tabz, half_geom(NZ, TZ), [&](int r) { return e[r]; },
+                                     [&](int l, T val) {
+                                       if (active) col[(long long)l * plane] = val;
+                                     });
 }
 
 template <typename T, int NP>
@@ -276,8 +350,8 @@ __global__ __launch_bounds__(192) void k_pass_b(T* __restrict__ W, const BoxDev*
 #pragma unroll
     for (int l = 0; l < NP; ++l) ex[q][l][lane] = v[l];
     const Half gz = half_geom(nz, tz);
-    fwd_bfly<T, NH>(tabz, gz, [&](int l) { return ex[q][l][lane]; },
-                    [&](int r, T val) { ex[q][r][lane] = val; });
+    fwd_bfly<T, NH, kPassBTwo<T>>(tabz, gz, [&](int l) { return ex[q][l][lane]; },
+                                  [&](int r, T val) { ex[q][r][lane] = val; });
   }
   __syncthreads();
 
@@ -307,10 +381,10 @@ __global__ __launch_bounds__(192) void k_pass_b(T* __restrict__ W, const BoxDev*
     __syncthreads();                              // every wave has read all three components
 #pragma unroll
     for (int rr = 0; rr < NP; ++rr) ex[q][rr][lane] = v[rr];
-    inv_bfly<T, NH>(tabz, half_geom(nz, tz), [&](int r) { return ex[q][r][lane]; },
-                    [&](int l, T val) {
-                      if (active) col[(long long)l * plane] = val;
-                    });
+    inv_bfly<T, NH, kPassBTwo<T>>(tabz, half_geom(nz, tz), [&](int r) { return ex[q][r][lane]; },
+                                  [&](int l, T val) {
+                                    if (active) col[(long long)l * plane] = val;
+                                  });
   }
 }
 

@@ -428,6 +428,7 @@ def test_autotune_keeps_results_bitwise():
         tune = h.autotune(r, h.new_vector())
         assert sum(t["chosen"] for t in tune) == 1 and all(t["apply_ms"] > 0 for t in tune)
         assert {t["streams"] for t in tune} == {1, 2}
+        assert {t["slab_order"] for t in tune} == {0, 1}
         z1 = h.new_vector()
         h.apply_precond(r, z1)
         assert torch.equal(z0, z1), prec
