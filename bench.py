@@ -235,25 +235,8 @@ def batch_leg(args, dev, log):
                 launch="hipGraph replay of the per-class, per-batch pass sequence")
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="c3")
-    ap.add_argument("--variants", default="fp32,bf16")
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--learned", type=int, default=1, help="run the C5 learned-correction leg")
-    ap.add_argument("--batch", type=int, default=1, help="run the 64-domain batch leg")
-    ap.add_argument("--pairs-rhs", type=int, default=100)
-    ap.add_argument("--pairs-per-rhs", type=int, default=20)
-    ap.add_argument("--epochs", type=int, default=150)
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py runs on one GPU only: the solver has no multi-GPU path "
-              "(see DESIGN.md for how it would shard)", file=sys.stderr)
-        sys.exit(2)
-
+def c3_context(args):
+    """Problem, device vectors and timing helpers of the 256^3 legs (child process)."""
     import torch
     from paper_2508_07193_amd import api, inputs
 
@@ -305,14 +288,23 @@ def main():
         return hh, dict(batch_boxes=c["batch_boxes"], streams=c["streams"], slab_order=c["slab_order"],
                         graph=True)
 
-    # ---------------- plain FP64 FlashMP
-    h, plan64 = tuned_handle("fp64")
+    return dict(torch=torch, P=P, b=b, n_unk=n_unk, run_solves=run_solves,
+                time_events=time_events, tuned_handle=tuned_handle)
+
+
+def main_leg(args):
+    """Plain FP64 FlashMP on the 256^3 workload: the bench value, rooflines, calibration."""
+    C = c3_context(args)
+    torch, b, n_unk = C["torch"], C["b"], C["n_unk"]
+    time_events = C["time_events"]
+    h, plan64 = C["tuned_handle"]("fp64")
     log(f"handle ready: workspace {h.ws.numel() / 2**20:.0f} MiB, vector {h.length} doubles")
-    x64, info64, tts64 = run_solves(h, args.steps, args.warmup, "fp64")
+    x64, info64, tts64 = C["run_solves"](h, args.steps, args.warmup, "fp64")
     z = h.new_vector()
     y = h.new_vector()
     t_pre = time_events(lambda: h.apply_precond(b, z), 10)
     t_spmv = time_events(lambda: h.curlcurl_apply(b, y), 20)
+
     def roof(name, kernel, bytes_per_launch, avg_ms, per):
         ach = bytes_per_launch / (avg_ms * 1e-3) / 1e9
         ratio = traffic_ratio(name)
@@ -350,7 +342,9 @@ def main():
     cal = torch.empty_like(b)
     t_copy = time_events(lambda: cal.copy_(b), 10)
     del cal
-    out = {
+    if args.ref_out:
+        np.save(args.ref_out, x64.cpu().numpy())
+    return {
         "metric": METRIC, "value": round(tts64, 2), "unit": "ms", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(tts64, 2),
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
@@ -373,41 +367,111 @@ def main():
                              "GB/s": round(16.0 * b.numel() / (t_copy * 1e-3) / 1e9, 1)},
         "variants": {},
     }
-    ref = x64.clone()
-    del h
-    torch.cuda.empty_cache()
 
-    for prec in [v for v in args.variants.split(",") if v]:
-        try:
-            hv, planv = tuned_handle(prec)
-            xv, infov, ttsv = run_solves(hv, max(1, args.steps), args.warmup, prec)
-            zv = hv.new_vector()
-            tpv = time_events(lambda: hv.apply_precond(b, zv), 10)
-            err = float(torch.linalg.vector_norm(xv - ref) / torch.linalg.vector_norm(ref))
-            out["variants"][prec] = dict(time_to_solution_ms=round(ttsv, 2),
-                                         iterations=infov["iterations"],
-                                         rel_residual_true=infov["rel_residual_true"],
-                                         precond_applies_per_s=round(1e3 / tpv, 1),
-                                         precond_ms=round(tpv, 4),
-                                         rel_err_vs_fp64_solution=err, precond_plan=planv,
-                                         speedup_vs_fp64=round(tts64 / ttsv, 3))
-            del hv
-            torch.cuda.empty_cache()
-        except Exception as e:  # report, do not hide
-            out["variants"][prec] = dict(error=str(e))
 
-    if args.batch:
-        try:
-            out["variants"]["batch_c4"] = batch_leg(args, dev, log)
-        except Exception as e:  # report, do not hide
-            out["variants"]["batch_c4"] = dict(error=str(e))
-    if args.learned:
-        try:
-            out["variants"]["learned_c5"] = learned_leg(args, dev, log)
-        except Exception as e:  # report, do not hide
-            out["variants"]["learned_c5"] = dict(error=str(e))
+def variant_leg(args):
+    """FP32 or BF16 transforms on the 256^3 workload, error against the FP64 solution."""
+    C = c3_context(args)
+    torch, b = C["torch"], C["b"]
+    hv, planv = C["tuned_handle"](args.prec)
+    xv, infov, ttsv = C["run_solves"](hv, max(1, args.steps), args.warmup, args.prec)
+    zv = hv.new_vector()
+    tpv = C["time_events"](lambda: hv.apply_precond(b, zv), 10)
+    out = dict(time_to_solution_ms=round(ttsv, 2), iterations=infov["iterations"],
+               rel_residual_true=infov["rel_residual_true"],
+               precond_applies_per_s=round(1e3 / tpv, 1), precond_ms=round(tpv, 4),
+               precond_plan=planv)
+    if args.ref_in:
+        ref = torch.from_numpy(np.load(args.ref_in)).to(xv.device)
+        out["rel_err_vs_fp64_solution"] = float(torch.linalg.vector_norm(xv - ref) /
+                                                torch.linalg.vector_norm(ref))
+    return out
+
+
+def run_leg(args):
+    dev = "cuda:0"
+    if args.leg == "main":
+        res = main_leg(args)
+    elif args.leg == "variant":
+        res = variant_leg(args)
+    elif args.leg == "batch":
+        res = batch_leg(args, dev, log)
+    elif args.leg == "learned":
+        res = learned_leg(args, dev, log)
+    else:
+        raise SystemExit(f"unknown leg {args.leg}")
+    print("LEG_RESULT " + json.dumps(res), flush=True)
+
+
+def child(args, leg, extra=()):
+    """Run one leg in a child process (each leg gets a fresh process and one
+    handle); its progress goes to our stderr, its result comes back as JSON."""
+    import subprocess
+    cmd = [sys.executable, "-u", os.path.abspath(__file__), "--leg", leg,
+           "--steps", str(args.steps), "--warmup", str(args.warmup), "--config", args.config,
+           "--pairs-rhs", str(args.pairs_rhs), "--pairs-per-rhs", str(args.pairs_per_rhs),
+           "--epochs", str(args.epochs)] + list(extra)
+    log(f"[bench] leg {leg} {' '.join(extra)}")
+    p = subprocess.run(cmd, stdout=subprocess.PIPE, text=True)
+    for line in p.stdout.splitlines():
+        if line.startswith("LEG_RESULT "):
+            return json.loads(line[len("LEG_RESULT "):])
+    return dict(error=f"leg {leg} ended with status {p.returncode} and no result")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c3")
+    ap.add_argument("--variants", default="fp32,bf16")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--learned", type=int, default=1, help="run the C5 learned-correction leg")
+    ap.add_argument("--batch", type=int, default=1, help="run the 64-domain batch leg")
+    ap.add_argument("--pairs-rhs", type=int, default=100)
+    ap.add_argument("--pairs-per-rhs", type=int, default=20)
+    ap.add_argument("--epochs", type=int, default=150)
+    ap.add_argument("--leg", default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--prec", default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--ref-out", default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--ref-in", default=None, help=argparse.SUPPRESS)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the solver has no multi-GPU path "
+              "(see DESIGN.md for how it would shard)", file=sys.stderr)
+        sys.exit(2)
+    if args.leg:
+        run_leg(args)
+        return
+
+    # This process never touches the GPU: each leg runs in a child process of
+    # its own and reports back, so one leg's failure is reported as that leg's
+    # error instead of ending the whole run.
+    import shutil
+    import tempfile
+    tmp = tempfile.mkdtemp(prefix="fmp_bench_")
+    ref = os.path.join(tmp, "x64.npy")
+    try:
+        out = child(args, "main", ["--ref-out", ref])
+        if "error" in out:
+            print(json.dumps(dict(metric=METRIC, value=None, unit="ms", n_gpus=1, error=out["error"])),
+                  flush=True)
+            sys.exit(1)
+        for prec in [v for v in args.variants.split(",") if v]:
+            r = child(args, "variant", ["--prec", prec, "--ref-in", ref])
+            if "time_to_solution_ms" in r:
+                r["speedup_vs_fp64"] = round(out["value"] / r["time_to_solution_ms"], 3)
+            out["variants"][prec] = r
+        if args.batch:
+            out["variants"]["batch_c4"] = child(args, "batch")
+        if args.learned:
+            out["variants"]["learned_c5"] = child(args, "learned")
+    finally:
+        shutil.rmtree(tmp, ignore_errors=True)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(P, info64["iterations"])
+        from paper_2508_07193_amd import inputs
+        out["cpu_baseline"] = cpu_baseline(inputs.make_problem(args.config), out["iterations"])
     print(json.dumps(out), flush=True)
 
 

@@ -59,7 +59,7 @@ struct StencilTile {
   int dom, x0, y0, z0;
 };
 
-constexpr int kStencilTX = 64, kStencilTY = 4, kStencilZC = 16;
+constexpr int kStencilTX = 64, kStencilTY = 8, kStencilZC = 64;
 
 // Workgroups of a launch are dealt to the 8 XCDs round-robin (block b runs on
 // XCD b % 8).  xcd_remap(b, nb) renumbers them so that each XCD works through

@@ -10,9 +10,10 @@
 // and the E_y, E_z rows follow by the cyclic relabelling x -> y -> z -> x.
 // Values outside the domain or on a wall slot are zero.
 //
-// Mapping: a workgroup owns a 64 x 4 tile of (i, j) columns and marches over
-// kStencilZC z-planes.  Three rolling LDS planes (k-1, k, k+1) of all three
-// components, with a one-cell halo in x and y, are filled by coalesced loads
+// Mapping: a workgroup owns a 64 x 8 tile of (i, j) columns and marches over
+// kStencilZC = 64 z-planes (the fastest of the tile shapes swept at 256^3).
+// Three rolling LDS planes (k-1, k, k+1) of all three components, with a
+// one-cell halo in x and y, are filled by coalesced loads
 // that zero wall slots and out-of-domain cells once, so the stencil itself
 // reads LDS without bounds checks.  Cell permittivities of planes k-1 and k
 // are staged the same way.  HBM sees each value once (halos come from L2),
@@ -145,11 +146,11 @@ __global__ __launch_bounds__(TX * TY) void k_curlcurl(const double* __restrict__
       sz = D.c / (0.25 * (((E[e0][ja - 1][ia - 1] + E[e0][ja][ia - 1]) + E[e0][ja - 1][ia]) +
                           E[e0][ja][ia]));
     }
-    if (i < nx && j < ny) {
+    if (i < nx && j < ny) {                      // y is not re-read here: streaming stores
       const long long o = ((long long)k * ny + j) * nx + i;
-      yb[o] = (j == 0 || k == 0) ? 0.0 : ex0 + sx * kx;
-      yb[cs + o] = (i == 0 || k == 0) ? 0.0 : ey0 + sy * ky;
-      yb[2 * cs + o] = (i == 0 || j == 0) ? 0.0 : ez0 + sz * kz;
+      __builtin_nontemporal_store((j == 0 || k == 0) ? 0.0 : ex0 + sx * kx, yb + o);
+      __builtin_nontemporal_store((i == 0 || k == 0) ? 0.0 : ey0 + sy * ky, yb + cs + o);
+      __builtin_nontemporal_store((i == 0 || j == 0) ? 0.0 : ez0 + sz * kz, yb + 2 * cs + o);
     }
     __syncthreads();
   }
