@@ -123,7 +123,7 @@ def learned_leg(args, dev, log):
     n = P["nx"]
     dom = dict(nx=n, ny=n, nz=n, c=P["c"], eps=P["eps"], eps_block=P["eps_block"], sub=P["sub"])
     h = api.Handle([dom], overlap=1, precision="fp64", use_learned=True, device=dev,
-                   batch_boxes=-1, use_graph=True)
+                   batch_boxes=-1, use_graph=False)
     h.autotune()
     t0 = time.perf_counter()
     X, Y = learned.generate_pairs(h, (n, n, n), args.pairs_rhs, args.pairs_per_rhs, 1005, log=log)
@@ -281,12 +281,12 @@ def c3_context(args):
 
     def tuned_handle(prec):
         hh = api.Handle([dom], overlap=1, precision=prec, device=dev, batch_boxes=-1,
-                        use_graph=True)
+                        use_graph=False)
         t = hh.autotune(b)
         c = [e for e in t if e["chosen"]][0]
         log(f"[{prec}] autotune: {[(e['batch_boxes'], e['streams'], e['slab_order'], round(e['apply_ms'], 4)) for e in t]}")
         return hh, dict(batch_boxes=c["batch_boxes"], streams=c["streams"], slab_order=c["slab_order"],
-                        graph=True)
+                        graph=False)
 
     return dict(torch=torch, P=P, b=b, n_unk=n_unk, run_solves=run_solves,
                 time_events=time_events, tuned_handle=tuned_handle)

@@ -191,7 +191,7 @@ typedef struct {
 } fmp_tune_entry;
 
 /* Autotuner of the preconditioner's launch plan: times fmp_apply_precond(r, z)
- * (three applies after a warm-up, or graph replays when use_graph is set) for
+ * as plain launch sequences (three applies after a warm-up) for
  * every candidate batch size (16 .. 1024 boxes and all boxes, per size class),
  * stream count and gather work order, and keeps the fastest plan.  Every plan
  * computes the same z bit for bit; only the schedule changes.  Requires a

@@ -707,10 +707,12 @@ fmp_status fmp_autotune(fmp_handle h, const double* r, double* z, fmp_tune_entry
   for (Cand& c : cands) {
     if ((st = use(c.batch, c.ns, c.slab)) != FMP_OK) break;
     if (c.ns > 1 && (int)h->launches.size() < c.ns) { c.ms = -1.0; continue; }   // no more overlap
-    if ((st = precond_apply(h, r, z, s, coarse)) != FMP_OK) break;      // capture / warm up
+    // candidates are timed as plain launch sequences (no capture per
+    // candidate); a graph-mode handle captures the chosen plan on first use
+    if ((st = precond_launches(h, r, z, s, coarse)) != FMP_OK) break;   // warm up
     HIPCHK(h, hipEventRecord(e0, s));
     constexpr int kReps = 3;
-    for (int k = 0; k < kReps && st == FMP_OK; ++k) st = precond_apply(h, r, z, s, coarse);
+    for (int k = 0; k < kReps && st == FMP_OK; ++k) st = precond_launches(h, r, z, s, coarse);
     if (st != FMP_OK) break;
     HIPCHK(h, hipEventRecord(e1, s));
     HIPCHK(h, hipEventSynchronize(e1));
