@@ -89,7 +89,7 @@ long long plan_batches(fmp_ctx* h, int batch) {
     for (size_t i = i0; i < i1; ++i) {
       BoxDev& B = h->boxes[h->order[i]];
       B.w_off = woff;                 // staging is reused batch after batch
-      woff += 3 * B.vol;
+      woff += (3 * box_wvol(B, h->prec == FMP_BF16) + 7) / 8 * 8;   // 16-byte aligned boxes
       nzmax = std::max(nzmax, B.nz);
     }
     wmax = std::max(wmax, woff);
@@ -354,6 +354,7 @@ fmp_status fmp_setup_subdomains(const fmp_domain_desc* domains, int32_t n_domain
           B.sx = X.own1 - X.own0; B.sy = Y.own1 - Y.own0; B.sz = Z.own1 - Z.own0;
           B.sub = h->nsub++;
           B.vol = (long long)B.nx * B.ny * B.nz;
+          B.wzp = (B.nz + 3) / 4 * 4;
           if (std::min(B.nx, std::min(B.ny, B.nz)) < 2) return FMP_ERR_INVALID_ARG;
           if (std::max(B.nx, std::max(B.ny, B.nz)) > kMaxSide) h->precond_ok = false;
           else sides_used[B.nx] = sides_used[B.ny] = sides_used[B.nz] = 1;

@@ -52,9 +52,17 @@ struct BoxDev {
   long long w_off;      // staging offset (elements) of component 0
   long long vol;        // nx*ny*nz
   double alpha;         // c / mean eps over the owned block
+  int wzp;              // MFMA staging: nz rounded up to 4 (chunks of 4 z values)
+  int pad_;
 };
 
-// Stencil tile: 64 x 4 columns marching over zc planes of one domain.
+// Staging elements of one component of a box: dense [z][y][x] for the
+// vector-ALU passes, z-fastest padded columns for the MFMA passes.
+__host__ __device__ inline long long box_wvol(const BoxDev& B, bool mfma) {
+  return mfma ? (long long)B.nx * B.ny * B.wzp : B.vol;
+}
+
+// Stencil tile: 64 x 8 columns marching over kStencilZC planes of one domain.
 struct StencilTile {
   int dom, x0, y0, z0;
 };

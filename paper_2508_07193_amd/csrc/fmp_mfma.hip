@@ -2,90 +2,146 @@
 //
 // Same three-pass structure and the same mathematics as the vector-ALU passes
 // (Sec. III-A Steps 1-3; Algorithm 1, exact_solve: forward DCT-II/DST-I per
-// component, closed-form 3x3 solve of eq. (12) per wavenumber, inverse), but
-// every directional contraction is a small GEMM on the matrix cores, the form
-// the paper gives its transforms (Sec. III-C, GEMM-based discrete transform):
-//   x-contraction of a z-slab: rows (z, y), K = x, N = p
-//   y-contraction:             rows (z, p), K = y, N = q
-//   z-contraction:             rows = 64 columns (y, x), K = z, N = r
-// Operands are rounded to bf16 (inputs when a fragment is loaded, tables at
-// setup), products accumulate in FP32, the block solve is FP32 and the staging
-// between passes is bf16.
+// component, closed-form 3x3 solve of eq. (12) per wavenumber, inverse), with
+// every directional contraction a small GEMM on the matrix cores, the form the
+// paper gives its transforms (Sec. III-C, GEMM-based discrete transform).
+// Operands are bf16 (inputs rounded once when they are staged, tables at
+// setup), products accumulate in FP32, the 3x3 solve is FP32.
 //
 // Fragment layout (16x16x32): lane l holds A[m = l%16][k = 8(l/16) .. +7],
-// B[k = 8(l/16) .. +7][n = l%16], and D[m = 4(l/16) + i][n = l%16], i < 4.
-// The tables are stored transposed for the B operand, Bt[n][k] with row
-// stride 64, so a lane's eight k values are one 16-byte load.
+// B[k = 8(l/16) .. +7][n = l%16] and D[m = 4(l/16) + i][n = l%16], i < 4.
+// A and B fragments are single 16-byte loads: every operand is stored with
+// its K index contiguous (tables row-major [out][in] with row stride 64; LDS
+// rows of KP + 8 bf16).  A D fragment holds four consecutive rows of one
+// column, which the passes arrange to be four consecutive elements in
+// memory, so each lane writes them with one 8-byte store.
+//
+// Staging W per box component: bf16 chunks of 4 consecutive z values,
+// ordered [z / 4][x'][y'] (y' fastest), so that a group of 16 lanes that
+// holds 4 z values of 16 consecutive columns reads or writes 128 contiguous
+// bytes in every pass.  A box component takes ceil(nz / 4) chunk planes.
+// Pass B needs no exchange between waves: a wave owns 16 columns of all three
+// components, so the 3x3 solve is done in registers.
+//   A  gather 4 z-planes -> x GEMM -> y GEMM -> W (one chunk per lane and tile)
+//   B  z GEMM -> solve -> inverse z GEMM, W -> W
+//   C  W (one chunk per column) -> inverse y GEMM -> inverse x GEMM -> scatter
+// LDS operands are never zero-filled: fragment elements beyond the valid K
+// range, and rows beyond the valid range, are masked to zero as they are read.
 #include "fmp_common.h"
 
 namespace fmp {
 namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int kTB = 64;   // bf16 table row stride
+constexpr int ZS = 4;     // z planes per pass A / C work item
 
-// D[row0 .. row0+16)[0 .. n_out) = sum_k A[row][k] Bt[n][k] for one wave;
-// A is read through aload(row, k) (0 outside), results go to dstore.
-template <int KP, class ALoad, class DStore>
-__device__ __forceinline__ void wave_gemm(int row0, int nrows, int n_out,
-                                          const __bf16* __restrict__ Bt, ALoad aload,
-                                          DStore dstore) {
-  const int lane = threadIdx.x & 63;
-  const int r = lane & 15, g = lane >> 4;
-  const int row = row0 + r;
-  bf16x8 a[KP / 32];
-#pragma unroll
-  for (int ks = 0; ks < KP / 32; ++ks)
-#pragma unroll
-    for (int j = 0; j < 8; ++j) a[ks][j] = (__bf16)(row < nrows ? aload(row, ks * 32 + 8 * g + j) : 0.f);
-  for (int n0 = 0; n0 < n_out; n0 += 16) {
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-    const int n = n0 + r;
-#pragma unroll
-    for (int ks = 0; ks < KP / 32; ++ks) {
-      const bf16x8 b = *reinterpret_cast<const bf16x8*>(Bt + n * kTB + ks * 32 + 8 * g);
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ks], b, acc, 0, 0, 0);
-    }
-#pragma unroll
-    for (int ii = 0; ii < 4; ++ii) {
-      const int rr = row0 + 4 * g + ii;
-      if (rr < nrows && n < n_out) dstore(rr, n, acc[ii]);
-    }
-  }
+template <int NP>
+struct Geo {
+  static constexpr int NT = (NP + 15) / 16;   // 16-wide tiles covering a side
+  static constexpr int NR = NT * 16;          // padded side
+  static constexpr int KS = (NP + 31) / 32;   // k-steps of 32
+  static constexpr int KP = KS * 32;          // padded K
+  static constexpr int RS = KP + 8;           // LDS row stride (bf16): spreads banks
+};
+
+__device__ __forceinline__ f32x4 mma(const bf16x8& a, const bf16x8& b, const f32x4& c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ bf16x8 ld8(const __bf16* p) {
+  return *reinterpret_cast<const bf16x8*>(p);
+}
+
+__device__ __forceinline__ bf16x8 zero8() {
+  const __bf16 z = (__bf16)0.f;
+  return bf16x8{z, z, z, z, z, z, z, z};
+}
+
+__device__ __forceinline__ bf16x4 zero4() {
+  const __bf16 z = (__bf16)0.f;
+  return bf16x4{z, z, z, z};
+}
+
+__device__ __forceinline__ bf16x4 pack4(const f32x4& v) {
+  return bf16x4{(__bf16)v[0], (__bf16)v[1], (__bf16)v[2], (__bf16)v[3]};
 }
 
 __device__ __forceinline__ bool box_wall(int q, int x, int y, int z) {
   return q == 0 ? (y == 0 || z == 0) : (q == 1 ? (x == 0 || z == 0) : (x == 0 || y == 0));
 }
 
-// e / d for 0 <= e < 2^24 from a precomputed 1/d (see the vector-ALU passes)
-__device__ __forceinline__ int qdiv(int e, double inv_d) { return (int)(((double)e + 0.5) * inv_d); }
-
-template <int NP>
-constexpr int zslab() {
-  return 256 / NP;
-}
-template <int NP>
-constexpr int kpad() {
-  return NP <= 32 ? 32 : 64;
+// one 16 x 16 output tile: sum over the k-steps of A(ks) x B(ks)
+template <int KS, class FA, class FB>
+__device__ __forceinline__ f32x4 tile_mma(FA a, FB b) {
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) acc = mma(a(ks), b(ks), acc);
+  return acc;
 }
 
-// The staging W between passes is bf16: every consumer rounds its MFMA
-// operands to bf16 anyway, so this halves the traffic at no cost in accuracy.
-// LDS slabs are dense [zl][y][x] (index = linear element id) in FP32.
+// table fragments for all output tiles: f[nt][ks] = T[16 nt + l%16][32 ks + 8(l/16) ..]
+template <int NT, int KS>
+__device__ __forceinline__ void load_tab(bf16x8 (&f)[NT][KS], const __bf16* T, int l16, int g) {
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) f[nt][ks] = ld8(T + (nt * 16 + l16) * kTB + 32 * ks + 8 * g);
+}
+
+template <int KS>
+__device__ __forceinline__ f32x4 tile_frag(const bf16x8 (&a)[KS], const bf16x8 (&b)[KS]) {
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) acc = mma(a[ks], b[ks], acc);
+  return acc;
+}
+
+// zero the elements of a fragment whose K index k0 + e is not below n
+__device__ __forceinline__ bf16x8 kmask(bf16x8 v, int k0, int n) {
+  typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+  u32x4 u = __builtin_bit_cast(u32x4, v);
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    const int k = k0 + 2 * d;
+    u[d] &= (k + 1 < n) ? 0xFFFFFFFFu : ((k < n) ? 0x0000FFFFu : 0u);
+  }
+  return __builtin_bit_cast(bf16x8, u);
+}
+
+// A fragments of this wave's NT row tiles (wave + 4 j) of an LDS operand;
+// rows for which ok(row) fails and K indices >= kn read as zero
+template <int NT, int KS, int RS, class OK>
+__device__ __forceinline__ void load_rows(bf16x8 (&a)[NT][KS], const __bf16* L, int wave, int l16,
+                                          int g, int kn, OK ok) {
+#pragma unroll
+  for (int j = 0; j < NT; ++j) {
+    const int row = (wave + 4 * j) * 16 + l16;
+    const bool rv = ok(row);
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+      a[j][ks] = rv ? kmask(ld8(L + row * RS + 32 * ks + 8 * g), 32 * ks + 8 * g, kn) : zero8();
+  }
+}
 
 // ---------------------------------------------------------------- pass A
+// One LDS buffer of ZS * NR rows, used twice: first the gathered slab
+// S[(zl, y)][x] (K = x contiguous), then, after every wave has moved its A
+// fragments into registers, the x-transformed slab Y[(p, zl)][y].  Wave w
+// owns the row tiles w, w + 4, ... (NT of them) in both GEMMs; table
+// fragments are loaded into registers once per block.
 template <int NP>
 __global__ __launch_bounds__(256) void k_mpass_a(const double* __restrict__ r, __bf16* __restrict__ W,
                                                  const BoxDev* __restrict__ boxes,
                                                  const DomainDev* __restrict__ doms,
                                                  const int4* __restrict__ work,
                                                  const __bf16* __restrict__ tb) {
-  constexpr int ZS = zslab<NP>(), KP = kpad<NP>();
-  constexpr int MAXE = (ZS * NP * NP + 255) / 256;
-  __shared__ float buf[ZS * NP * NP];
-  __shared__ float obuf[ZS * NP * NP];
+  using G = Geo<NP>;
+  constexpr int NR = G::NR, KS = G::KS, RS = G::RS, NT = G::NT;
+  constexpr int ROWS = ZS * NR;
+  __shared__ __align__(16) __bf16 S[ROWS * RS];
   const int4 wk = work[xcd_remap(blockIdx.x, gridDim.x)];
   const BoxDev& B = boxes[wk.x];
   const int q = wk.y, z0 = wk.z;
@@ -93,121 +149,167 @@ __global__ __launch_bounds__(256) void k_mpass_a(const double* __restrict__ r, _
   const int nzs = min(ZS, nz - z0);
   const DomainDev& D = doms[B.dom];
   const double* src = r + D.offset + (long long)q * D.nz * D.ny * D.nx;
-  const int plane = ny * nx, tot = nzs * plane;
-  const int t = threadIdx.x, wave = t >> 6;
-  const double inv_plane = 1.0 / plane, inv_nx = 1.0 / nx;
-  double vals[MAXE];
-  unsigned wall = 0;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int l16 = lane & 15, g = lane >> 4;
+  bf16x8 tx[NT][KS], ty[NT][KS], a[NT][KS];
+  load_tab(tx, tb + (q == 0 ? B.mdct[0] : B.mdst[0]), l16, g);
+
+  {  // S^gamma: the slab's nzs * ny * nx elements, walls as zero; loads first
+    const int plane = ny * nx, tot = nzs * plane;
+    const float inv_plane = 1.f / (float)plane, inv_nx = 1.f / (float)nx;
+    constexpr int NI = (ZS * NP * NP + 255) / 256;
+    double v[NI];
+    int at[NI];
+    unsigned long long wall = 0;
 #pragma unroll
-  for (int i = 0; i < MAXE; ++i) {
-    const int e = min(t + 256 * i, tot - 1);
-    const int zl = qdiv(e, inv_plane), rem = e - zl * plane;
-    const int y = qdiv(rem, inv_nx), x = rem - y * nx;
-    if (box_wall(q, x, y, z0 + zl)) wall |= 1u << i;
-    vals[i] = src[((B.bz0 + z0 + zl) * D.ny + (B.by0 + y)) * D.nx + (B.bx0 + x)];
-  }
+    for (int i = 0; i < NI; ++i) {
+      const int e = min(t + 256 * i, tot - 1);
+      const int zl = (int)(((float)e + 0.5f) * inv_plane), rem = e - zl * plane;
+      const int y = (int)(((float)rem + 0.5f) * inv_nx), x = rem - y * nx;
+      v[i] = src[((long long)(B.bz0 + z0 + zl) * D.ny + (B.by0 + y)) * D.nx + (B.bx0 + x)];
+      at[i] = (zl * NR + y) * RS + x;
+      if (box_wall(q, x, y, z0 + zl)) wall |= 1ull << i;
+    }
 #pragma unroll
-  for (int i = 0; i < MAXE; ++i) {
-    const int e = t + 256 * i;
-    if (e < tot) buf[e] = ((wall >> i) & 1u) ? 0.f : (float)vals[i];
+    for (int i = 0; i < NI; ++i)
+      if (t + 256 * i < tot) S[at[i]] = (__bf16)(((wall >> i) & 1ull) ? 0.0 : v[i]);
   }
   __syncthreads();
-  {  // x: rows rho = (zl, y) at buf[rho * nx], K = x, N = p
-    const __bf16* Bt = tb + (q == 0 ? B.mdct[0] : B.mdst[0]);
-    const int R = nzs * ny;
-    for (int tile = wave; tile * 16 < R; tile += 4)
-      wave_gemm<KP>(tile * 16, R, nx, Bt,
-                    [&](int rho, int k) { return k < nx ? buf[rho * nx + k] : 0.f; },
-                    [&](int rho, int p, float v) { obuf[rho * nx + p] = v; });
+
+  // x: D[(zl, y)][p] = sum_x S[(zl, y)][x] T[p][x]
+  load_rows<NT, KS, RS>(a, S, wave, l16, g, nx,
+                        [&](int row) { return row % NR < ny && row / NR < nzs; });
+  __syncthreads();                                // S is overwritten by Y from here
+  load_tab(ty, tb + (q == 1 ? B.mdct[1] : B.mdst[1]), l16, g);
+#pragma unroll
+  for (int j = 0; j < NT; ++j) {
+    const int row = (wave + 4 * j) * 16 + 4 * g, zl = row / NR, y = row - zl * NR;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {             // lane: Y[(p, zl)][y .. y+3]
+      const int p = nt * 16 + l16;
+      *reinterpret_cast<bf16x4*>(S + (p * ZS + zl) * RS + y) = pack4(tile_frag<KS>(a[j], tx[nt]));
+    }
   }
   __syncthreads();
-  {  // y: rows rho = (zl, p), K = y, N = q
-    const __bf16* Bt = tb + (q == 1 ? B.mdct[1] : B.mdst[1]);
-    const int R = nzs * nx;
-    for (int tile = wave; tile * 16 < R; tile += 4)
-      wave_gemm<KP>(tile * 16, R, ny, Bt,
-                    [&](int rho, int k) {
-                      const int zl = qdiv(rho, inv_nx), p = rho - zl * nx;
-                      return k < ny ? obuf[zl * plane + k * nx + p] : 0.f;
-                    },
-                    [&](int rho, int qq, float v) {
-                      const int zl = qdiv(rho, inv_nx), p = rho - zl * nx;
-                      buf[zl * plane + qq * nx + p] = v;
-                    });
+
+  // y: D[(p, zl)][q'] = sum_y Y[(p, zl)][y] T[q'][y]  ->  chunk z0 / 4 of column (p, q')
+  load_rows<NT, KS, RS>(a, S, wave, l16, g, ny, [](int) { return true; });
+  __bf16* Wc = W + B.w_off + (long long)q * box_wvol(B, true) + (long long)(z0 / 4) * ny * nx * 4;
+#pragma unroll
+  for (int j = 0; j < NT; ++j) {
+    const int p = (wave + 4 * j) * 4 + g;         // the lane's rows: (p, zl = 0..3)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const int qq = nt * 16 + l16;
+      const f32x4 acc = tile_frag<KS>(a[j], ty[nt]);
+      if (p < nx && qq < ny) *reinterpret_cast<bf16x4*>(Wc + (p * ny + qq) * 4) = pack4(acc);
+    }
   }
-  __syncthreads();
-  __bf16* dst = W + B.w_off + (long long)q * B.vol + (long long)z0 * plane;
-  for (int e = t; e < tot; e += 256) dst[e] = (__bf16)buf[e];
 }
 
 // ---------------------------------------------------------------- pass B
+// Wave w of a block owns the 16 columns c0 + 16 w + (0..15) of all three
+// components.  Forward z as D[r][c] = sum_z T[r][z] X[z][c] (table = A,
+// column data = B, read straight from W), solve in registers, inverse z as
+// D[z][c] = sum_r Ti[z][r] E[r][c] with E restaged through the wave's LDS rows
+// (r contiguous per column).
 template <int NP>
 __global__ __launch_bounds__(256) void k_mpass_b(__bf16* __restrict__ W,
                                                  const BoxDev* __restrict__ boxes,
                                                  const int4* __restrict__ work,
                                                  const __bf16* __restrict__ tb,
                                                  const float* __restrict__ sig) {
-  constexpr int KP = kpad<NP>();
-  constexpr int MAXE = (3 * NP * 64 + 255) / 256;
-  __shared__ float L[3][NP][64];
-  __shared__ float X[3][NP][64];
+  using G = Geo<NP>;
+  constexpr int NT = G::NT, KS = G::KS, KP = G::KP, RS = G::RS;
+  __shared__ __align__(16) __bf16 E[4][3][16][RS];
   const int4 wk = work[xcd_remap(blockIdx.x, gridDim.x)];
   const BoxDev& B = boxes[wk.x];
-  const int nx = B.nx, ny = B.ny, nz = B.nz;
-  const int plane = ny * nx, c0 = wk.y;
-  const int t = threadIdx.x, wave = t >> 6;
-  const int n3 = 3 * nz * 64;
-  float vals[MAXE];
+  const int nx = B.nx, ny = B.ny, nz = B.nz, nzc = B.wzp / 4;
+  const int plane = ny * nx;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int l16 = lane & 15, g = lane >> 4;
+  const int c = wk.y + 16 * wave + l16;
+  const bool active = c < plane;
+  const long long wv = box_wvol(B, true);
+  const __bf16* col0 = W + B.w_off + (long long)min(c, plane - 1) * 4;   // chunk 0 of column c
+
+  // column fragments X[z = 32 ks + 8 g ..][c] (two chunks each), zero beyond nz
+  bf16x8 xb[3][KS];
 #pragma unroll
-  for (int i = 0; i < MAXE; ++i) {                // column slab of the three components
-    const int e = min(t + 256 * i, n3 - 1);
-    const int q = e / (nz * 64), rem = e - q * nz * 64, l = rem >> 6, c = rem & 63;
-    vals[i] = (float)W[B.w_off + q * B.vol + (long long)l * plane + min(c0 + c, plane - 1)];
-  }
+  for (int qq = 0; qq < 3; ++qq)
 #pragma unroll
-  for (int i = 0; i < MAXE; ++i) {
-    const int e = t + 256 * i;
-    if (e < n3) {
-      const int q = e / (nz * 64), rem = e - q * nz * 64, l = rem >> 6, c = rem & 63;
-      L[q][l][c] = vals[i];
+    for (int ks = 0; ks < KS; ++ks) {
+      const int ch = 8 * ks + 2 * g;
+      const bf16x4 lo = ch < nzc ? *reinterpret_cast<const bf16x4*>(col0 + qq * wv + (long long)ch * plane * 4) : zero4();
+      const bf16x4 hi = ch + 1 < nzc ? *reinterpret_cast<const bf16x4*>(col0 + qq * wv + (long long)(ch + 1) * plane * 4) : zero4();
+      bf16x8 v = bf16x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+      xb[qq][ks] = kmask(v, 4 * ch, nz);
+    }
+  const __bf16* Tst = tb + B.mdst[2];             // DST-I along z (E_x, E_y): symmetric
+  const __bf16* Tct = tb + B.mdct[2];             // DCT-II along z (E_z)
+  const __bf16* Tci = tb + B.mdctT[2];            // its transpose
+  f32x4 acc[3][NT];
+#pragma unroll
+  for (int mt = 0; mt < NT; ++mt) {
+    const int rrow = mt * 16 + l16;
+#pragma unroll
+    for (int qq = 0; qq < 3; ++qq) {
+      const __bf16* T = qq == 2 ? Tct : Tst;
+      acc[qq][mt] = tile_mma<KS>([&](int ks) { return ld8(T + rrow * kTB + 32 * ks + 8 * g); },
+                                 [&](int ks) { return xb[qq][ks]; });
     }
   }
-  __syncthreads();
-  for (int task = wave; task < 12; task += 4) {        // forward z, 3 components x 4 row tiles
-    const int q = task >> 2, tile = task & 3;
-    const __bf16* Bt = tb + (q == 2 ? B.mdct[2] : B.mdst[2]);
-    wave_gemm<KP>(tile * 16, 64, nz, Bt, [&](int c, int l) { return l < nz ? L[q][l][c] : 0.f; },
-                  [&](int c, int rr, float v) { X[q][rr][c] = v; });
-  }
-  __syncthreads();
+
+  // e = (r + alpha s (s.r)) / (1 + alpha |s|^2) at wavenumbers (x, y, r)
+  const int cc = active ? c : 0;
+  const int xx = cc / ny, yy = cc - xx * ny;          // columns are (x', y'), y' fastest
+  const float sx = sig[B.sig[0] + xx], sy = sig[B.sig[1] + yy];
   const float alpha = (float)B.alpha;
-  for (int e = t; e < nz * 64; e += 256) {             // e = (r + alpha s (s.r)) / (1 + alpha |s|^2)
-    const int rr = e >> 6, c = e & 63, col = min(c0 + c, plane - 1);
-    const int yy = col / nx, xx = col - yy * nx;
-    const float sx = sig[B.sig[0] + xx], sy = sig[B.sig[1] + yy], sz = sig[B.sig[2] + rr];
-    const float a = X[0][rr][c], b = X[1][rr][c], d = X[2][rr][c];
-    const float dot = __builtin_fmaf(sx, a, __builtin_fmaf(sy, b, sz * d));
-    const float inv = 1.f / __builtin_fmaf(alpha, __builtin_fmaf(sx, sx, __builtin_fmaf(sy, sy, sz * sz)), 1.f);
-    const float ad = alpha * dot;
-    X[0][rr][c] = __builtin_fmaf(ad, sx, a) * inv;
-    X[1][rr][c] = __builtin_fmaf(ad, sy, b) * inv;
-    X[2][rr][c] = __builtin_fmaf(ad, sz, d) * inv;
+  const float sxy2 = __builtin_fmaf(sx, sx, sy * sy);
+#pragma unroll
+  for (int mt = 0; mt < NT; ++mt)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int rr = mt * 16 + 4 * g + i;
+      const float sz = sig[B.sig[2] + min(rr, nz - 1)];
+      const float a = acc[0][mt][i], b = acc[1][mt][i], d = acc[2][mt][i];
+      const float dot = __builtin_fmaf(sx, a, __builtin_fmaf(sy, b, sz * d));
+      const float inv = 1.f / __builtin_fmaf(alpha, __builtin_fmaf(sz, sz, sxy2), 1.f);
+      const float ad = alpha * dot;
+      const bool ok = rr < nz;
+      acc[0][mt][i] = ok ? __builtin_fmaf(ad, sx, a) * inv : 0.f;
+      acc[1][mt][i] = ok ? __builtin_fmaf(ad, sy, b) * inv : 0.f;
+      acc[2][mt][i] = ok ? __builtin_fmaf(ad, sz, d) * inv : 0.f;
+    }
+#pragma unroll
+  for (int qq = 0; qq < 3; ++qq) {
+#pragma unroll
+    for (int mt = 0; mt < NT; ++mt)
+      *reinterpret_cast<bf16x4*>(&E[wave][qq][l16][mt * 16 + 4 * g]) = pack4(acc[qq][mt]);
+    if (KP > NT * 16)                             // K padding of the inverse
+      *reinterpret_cast<bf16x4*>(&E[wave][qq][l16][NT * 16 + (4 * g) % (KP - NT * 16)]) = zero4();
   }
   __syncthreads();
-  for (int task = wave; task < 12; task += 4) {        // inverse z
-    const int q = task >> 2, tile = task & 3;
-    const __bf16* Bt = tb + (q == 2 ? B.mdctT[2] : B.mdst[2]);
-    wave_gemm<KP>(tile * 16, 64, nz, Bt, [&](int c, int rr) { return rr < nz ? X[q][rr][c] : 0.f; },
-                  [&](int c, int l, float v) { L[q][l][c] = v; });
-  }
-  __syncthreads();
-  for (int e = t; e < n3; e += 256) {
-    const int q = e / (nz * 64), rem = e - q * nz * 64, l = rem >> 6, c = rem & 63;
-    if (c0 + c < plane) W[B.w_off + q * B.vol + (long long)l * plane + c0 + c] = (__bf16)L[q][l][c];
+
+#pragma unroll
+  for (int mt = 0; mt < NT; ++mt) {
+    const int zrow = mt * 16 + l16;
+#pragma unroll
+    for (int qq = 0; qq < 3; ++qq) {
+      const __bf16* T = qq == 2 ? Tci : Tst;
+      const f32x4 o = tile_mma<KS>([&](int ks) { return ld8(T + zrow * kTB + 32 * ks + 8 * g); },
+                                   [&](int ks) { return ld8(&E[wave][qq][l16][32 * ks + 8 * g]); });
+      const int ch = mt * 4 + g;                    // the lane's rows: chunk ch of column c
+      if (active && ch < nzc)
+        *reinterpret_cast<bf16x4*>(W + B.w_off + qq * wv + ((long long)ch * plane + c) * 4) = pack4(o);
+    }
   }
 }
 
 // ---------------------------------------------------------------- pass C
+// One LDS buffer used twice, as in pass A: the slab X[(p, zl)][q'] (K = q',
+// the spectral y index), then U[(y, zl)][p] after the inverse y GEMM (K = p,
+// the spectral x index).
 template <int NP>
 __global__ __launch_bounds__(256) void k_mpass_c(const __bf16* __restrict__ W, double* __restrict__ z,
                                                  const BoxDev* __restrict__ boxes,
@@ -215,66 +317,77 @@ __global__ __launch_bounds__(256) void k_mpass_c(const __bf16* __restrict__ W, d
                                                  const int4* __restrict__ work,
                                                  const __bf16* __restrict__ tb,
                                                  const double* __restrict__ coarse, int nsub) {
-  constexpr int ZS = zslab<NP>(), KP = kpad<NP>();
-  constexpr int MAXE = (ZS * NP * NP + 255) / 256;
-  __shared__ float buf[ZS * NP * NP];
-  __shared__ float obuf[ZS * NP * NP];
+  using G = Geo<NP>;
+  constexpr int NR = G::NR, KS = G::KS, RS = G::RS, NT = G::NT;
+  constexpr int ROWS = ZS * NR;
+  __shared__ __align__(16) __bf16 X[ROWS * RS];
   const int4 wk = work[xcd_remap(blockIdx.x, gridDim.x)];
   const BoxDev& B = boxes[wk.x];
   const int q = wk.y, z0 = wk.z;
   const int nx = B.nx, ny = B.ny, nz = B.nz;
   const int nzs = min(ZS, nz - z0);
-  const int plane = ny * nx, tot = nzs * plane;
-  const int t = threadIdx.x, wave = t >> 6;
-  const double inv_nx = 1.0 / nx;
-  const __bf16* srcw = W + B.w_off + (long long)q * B.vol + (long long)z0 * plane;
-  float vals[MAXE];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int l16 = lane & 15, g = lane >> 4;
+  const int lz0 = B.oz0 - B.bz0, lz1 = lz0 + B.sz;
+  const int ly0 = B.oy0 - B.by0, ly1 = ly0 + B.sy;
+  const int lx0 = B.ox0 - B.bx0, lx1 = lx0 + B.sx;
+  if (z0 + ZS <= lz0 || z0 >= lz1) return;         // no owned plane in this slab
+  bf16x8 ty[NT][KS], tx[NT][KS], a[NT][KS];
+  load_tab(ty, tb + (q == 1 ? B.mdctT[1] : B.mdst[1]), l16, g);
+  load_tab(tx, tb + (q == 0 ? B.mdctT[0] : B.mdst[0]), l16, g);
+
+  {  // chunk z0 / 4 of the slab's columns (p, q'): X[(p, zl)][q']
+    const int plane = ny * nx;
+    const __bf16* Wc = W + B.w_off + (long long)q * box_wvol(B, true) + (long long)(z0 / 4) * plane * 4;
+    const float inv_ny = 1.f / (float)ny;
+    for (int e = t; e < plane; e += 256) {
+      const int p = (int)(((float)e + 0.5f) * inv_ny), qq = e - p * ny;
+      const bf16x4 v = *reinterpret_cast<const bf16x4*>(Wc + e * 4);
 #pragma unroll
-  for (int i = 0; i < MAXE; ++i) vals[i] = (float)srcw[min(t + 256 * i, tot - 1)];
-#pragma unroll
-  for (int i = 0; i < MAXE; ++i)
-    if (t + 256 * i < tot) buf[t + 256 * i] = vals[i];
-  __syncthreads();
-  {  // y inverse: rows rho = (zl, p), K = q, N = m
-    const __bf16* Bt = tb + (q == 1 ? B.mdctT[1] : B.mdst[1]);
-    const int R = nzs * nx;
-    for (int tile = wave; tile * 16 < R; tile += 4)
-      wave_gemm<KP>(tile * 16, R, ny, Bt,
-                    [&](int rho, int k) {
-                      const int zl = qdiv(rho, inv_nx), p = rho - zl * nx;
-                      return k < ny ? buf[zl * plane + k * nx + p] : 0.f;
-                    },
-                    [&](int rho, int m, float v) {
-                      const int zl = qdiv(rho, inv_nx), p = rho - zl * nx;
-                      obuf[zl * plane + m * nx + p] = v;
-                    });
+      for (int zl = 0; zl < ZS; ++zl) X[(p * ZS + zl) * RS + qq] = v[zl];
+    }
   }
   __syncthreads();
-  {  // x inverse: rows rho = (zl, y) at obuf[rho * nx], K = p, N = l
-    const __bf16* Bt = tb + (q == 0 ? B.mdctT[0] : B.mdst[0]);
-    const int R = nzs * ny;
-    for (int tile = wave; tile * 16 < R; tile += 4)
-      wave_gemm<KP>(tile * 16, R, nx, Bt,
-                    [&](int rho, int k) { return k < nx ? obuf[rho * nx + k] : 0.f; },
-                    [&](int rho, int l, float v) { buf[rho * nx + l] = v; });
+
+  // inverse y: D[(p, zl)][m] = sum_q' X[(p, zl)][q'] Ti[m][q']; rows p >= nx read as zero
+  load_rows<NT, KS, RS>(a, X, wave, l16, g, ny, [&](int row) { return row / ZS < nx; });
+  __syncthreads();                                // X is overwritten by U from here
+#pragma unroll
+  for (int j = 0; j < NT; ++j) {
+    const int p = (wave + 4 * j) * 4 + g;         // the lane's rows: (p, zl = 0..3)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const int m = nt * 16 + l16;
+      const f32x4 acc = tile_frag<KS>(a[j], ty[nt]);
+#pragma unroll
+      for (int zl = 0; zl < ZS; ++zl) X[(m * ZS + zl) * RS + p] = (__bf16)acc[zl];
+    }
   }
   __syncthreads();
-  const int lz0 = max(z0, B.oz0 - B.bz0), lz1 = min(z0 + nzs, B.oz0 - B.bz0 + B.sz);
-  if (lz1 <= lz0) return;
-  const int ly0 = B.oy0 - B.by0, lx0 = B.ox0 - B.bx0;
-  const int oplane = B.sy * B.sx, otot = (lz1 - lz0) * oplane;
+
+  // inverse x: D[(y, zl)][l] = sum_p U[(y, zl)][p] Ti[l][p], then S^0T
+  load_rows<NT, KS, RS>(a, X, wave, l16, g, nx, [](int) { return true; });
   const DomainDev& D = doms[B.dom];
   double* dst = z + D.offset + (long long)q * D.nz * D.ny * D.nx;
   const double cq = coarse ? coarse[(long long)q * nsub + B.sub] : 0.0;
-  const double inv_op = 1.0 / oplane, inv_sx = 1.0 / B.sx;
-  for (int e = t; e < otot; e += 256) {
-    const int zl = qdiv(e, inv_op), rem = e - zl * oplane;
-    const int y = qdiv(rem, inv_sx), x = rem - y * B.sx;
-    const int lz = lz0 + zl, ly = ly0 + y, lx = lx0 + x;
-    const int gz = B.bz0 + lz, gy = B.by0 + ly, gx = B.bx0 + lx;
-    double val = (double)buf[(lz - z0) * plane + ly * nx + lx];
-    if (coarse && !box_wall(q, gx, gy, gz)) val += cq;
-    dst[(gz * D.ny + gy) * D.nx + gx] = val;
+#pragma unroll
+  for (int j = 0; j < NT; ++j) {
+    const int y = (wave + 4 * j) * 4 + g;         // the lane's rows: (y, zl = 0..3)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const int x = nt * 16 + l16;
+      const f32x4 acc = tile_frag<KS>(a[j], tx[nt]);
+      if (y < ly0 || y >= ly1 || x < lx0 || x >= lx1) continue;
+#pragma unroll
+      for (int zl = 0; zl < ZS; ++zl) {
+        const int lz = z0 + zl;
+        if (zl >= nzs || lz < lz0 || lz >= lz1) continue;
+        const int gz = B.bz0 + lz, gy = B.by0 + y, gx = B.bx0 + x;
+        double val = (double)acc[zl];
+        if (coarse && !box_wall(q, gx, gy, gz)) val += cq;
+        dst[((long long)gz * D.ny + gy) * D.nx + gx] = val;
+      }
+    }
   }
 }
 
@@ -293,7 +406,7 @@ __global__ __launch_bounds__(256) void k_mpass_c(const __bf16* __restrict__ W, d
 
 }  // namespace
 
-int mfma_zslab(int cls) { return 256 / kClasses[cls]; }
+int mfma_zslab(int) { return ZS; }
 
 hipError_t launch_mfma_pass_a(int cls, const double* r, void* Wv, const BoxDev* boxes,
                               const DomainDev* doms, const int4* work, int nwork,
