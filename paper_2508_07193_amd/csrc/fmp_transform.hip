@@ -355,6 +355,8 @@ __global__ __launch_bounds__(192) void k_pass_b(T* __restrict__ W, const BoxDev*
   }
   __syncthreads();
 
+  // e = (r + alpha s (s.r)) / (1 + alpha |s|^2): wave q solves the wavenumbers
+  // rr = q, q + 3, ... for all three components, in place
   const int yy = active ? c / nx : 0;
   const int xx = active ? c - yy * nx : 0;
   const T sx = tab[B.sig[0] + xx];
@@ -363,14 +365,21 @@ __global__ __launch_bounds__(192) void k_pass_b(T* __restrict__ W, const BoxDev*
   const T alpha = (T)B.alpha;
   const T sxy2 = fmaT<T>(sx, sx, sy * sy);
 #pragma unroll
-  for (int rr = 0; rr < NP; ++rr) {               // e = (r + alpha s (s.r)) / (1 + alpha |s|^2)
-    const T s3 = sz[rr];
-    const T a = ex[0][rr][lane], b = ex[1][rr][lane], d = ex[2][rr][lane];
-    const T dot = fmaT<T>(sx, a, fmaT<T>(sy, b, s3 * d));
-    const T sq = q == 0 ? sx : (q == 1 ? sy : s3);
-    const T rq = q == 0 ? a : (q == 1 ? b : d);
-    v[rr] = fmaT<T>(alpha * sq, dot, rq) * recip<T>(fmaT<T>(alpha, fmaT<T>(s3, s3, sxy2), T(1)));
+  for (int i = 0; i < (NP + 2) / 3; ++i) {
+    const int rr = q + 3 * i;
+    if (rr < NP) {
+      const T s3 = sz[rr];
+      const T a = ex[0][rr][lane], b = ex[1][rr][lane], d = ex[2][rr][lane];
+      const T dot = fmaT<T>(sx, a, fmaT<T>(sy, b, s3 * d));
+      const T inv = recip<T>(fmaT<T>(alpha, fmaT<T>(s3, s3, sxy2), T(1)));
+      ex[0][rr][lane] = fmaT<T>(alpha * sx, dot, a) * inv;
+      ex[1][rr][lane] = fmaT<T>(alpha * sy, dot, b) * inv;
+      ex[2][rr][lane] = fmaT<T>(alpha * s3, dot, d) * inv;
+    }
   }
+  __syncthreads();
+#pragma unroll
+  for (int rr = 0; rr < NP; ++rr) v[rr] = ex[q][rr][lane];
   if (form == 0) {
     if (tz == 0) colz_inv<T, NP, NP, 0>(tabz, v, col, plane, active);
     else colz_inv<T, NP, NP, 1>(tabz, v, col, plane, active);
@@ -378,9 +387,6 @@ __global__ __launch_bounds__(192) void k_pass_b(T* __restrict__ W, const BoxDev*
     if (tz == 0) colz_inv<T, NP, NP - 1, 0>(tabz, v, col, plane, active);
     else colz_inv<T, NP, NP - 1, 1>(tabz, v, col, plane, active);
   } else {
-    __syncthreads();                              // every wave has read all three components
-#pragma unroll
-    for (int rr = 0; rr < NP; ++rr) ex[q][rr][lane] = v[rr];
     inv_bfly<T, NH, kPassBTwo<T>>(tabz, half_geom(nz, tz), [&](int r) { return ex[q][r][lane]; },
                                   [&](int l, T val) {
                                     if (active) col[(long long)l * plane] = val;
