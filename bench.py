@@ -235,6 +235,46 @@ def batch_leg(args, dev, log):
                 launch="hipGraph replay of the per-class, per-batch pass sequence")
 
 
+def convergence_leg(args, dev, log):
+    """Shape of the overlap study of Sec. IV (convergence experiments): uniform
+    medium, b = A x_rand, stopping at relative residual 1e-12; no
+    preconditioner versus RAS with overlap 1, 2, 3, each under BiCGSTAB and
+    FGMRES(30).  128^3 grid, 4^3 subdomains of 32^3, c = 2, FP64 transforms.
+    (Overlap 0 is not admissible with PEC-box subdomains: the interface
+    unknowns would sit on box walls and never be corrected.)"""
+    import torch
+    from paper_2508_07193_amd import api, inputs
+    n, sub, c = 128, 32, 2.0
+    xr = torch.from_numpy(inputs.normal_rhs(np.random.default_rng(11), n, n, n).ravel()).to(dev)
+    dom = [dict(nx=n, ny=n, nz=n, c=c, sub=(sub, sub, sub))]
+    rows = []
+    for g in (0, 1, 2, 3):
+        h = api.Handle(dom, overlap=max(g, 1), precision="fp64", device=dev)
+        b = h.new_vector()
+        h.curlcurl_apply(xr, b)
+        x = h.new_vector()
+        for solver in ("bicgstab", "fgmres"):
+            kw = dict(solver=solver, rtol=1e-12, max_iter=3000, precond=g > 0)
+            x.zero_()
+            h.solve(b, x, **kw)
+            x.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = h.solve(b, x, **kw)
+            torch.cuda.synchronize()
+            tts = (time.perf_counter() - t0) * 1e3
+            err = float(torch.linalg.vector_norm(x - xr) / torch.linalg.vector_norm(xr))
+            rows.append(dict(precond=f"ras_overlap{g}" if g else "none", solver=solver,
+                             iterations=info["iterations"], time_to_solution_ms=round(tts, 2),
+                             rel_residual_true=info["rel_residual_true"], rel_err_vs_x_rand=err,
+                             status=info["status"]))
+            log(f"[convergence] {rows[-1]}")
+        h.close()
+    return dict(workload="128^3 Yee grid, PEC walls, eps 1, c=2, 4^3 subdomains of 32^3, "
+                         "b = A x_rand (x_rand N(0,1) seed 11), rel. residual 1e-12",
+                rows=rows)
+
+
 def c3_context(args):
     """Problem, device vectors and timing helpers of the 256^3 legs (child process)."""
     import torch
@@ -398,6 +438,8 @@ def run_leg(args):
         res = batch_leg(args, dev, log)
     elif args.leg == "learned":
         res = learned_leg(args, dev, log)
+    elif args.leg == "convergence":
+        res = convergence_leg(args, dev, log)
     else:
         raise SystemExit(f"unknown leg {args.leg}")
     print("LEG_RESULT " + json.dumps(res), flush=True)
@@ -429,6 +471,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--learned", type=int, default=1, help="run the C5 learned-correction leg")
     ap.add_argument("--batch", type=int, default=1, help="run the 64-domain batch leg")
+    ap.add_argument("--convergence", type=int, default=1,
+                    help="run the overlap / solver convergence study leg (128^3)")
     ap.add_argument("--pairs-rhs", type=int, default=100)
     ap.add_argument("--pairs-per-rhs", type=int, default=20)
     ap.add_argument("--epochs", type=int, default=150)
@@ -467,6 +511,8 @@ def main():
             out["variants"]["batch_c4"] = child(args, "batch")
         if args.learned:
             out["variants"]["learned_c5"] = child(args, "learned")
+        if args.convergence:
+            out["variants"]["convergence_overlap"] = child(args, "convergence")
     finally:
         shutil.rmtree(tmp, ignore_errors=True)
     if not args.no_cpu:

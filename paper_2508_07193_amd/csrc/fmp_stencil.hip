@@ -57,6 +57,7 @@ __global__ __launch_bounds__(TX * TY) void k_curlcurl(const double* __restrict__
   double pre[NE], epre[NEE];
   unsigned ok_mask = 0;
   auto fetch = [&](int kk) {
+    static_assert(NE <= 32, "validity flags are kept in one 32-bit mask");
     ok_mask = 0;
 #pragma unroll
     for (int i = 0; i < NE; ++i) {

@@ -256,20 +256,21 @@ __global__ __launch_bounds__(kAC) void k_pass_a(const double* __restrict__ r, T*
   const int t = threadIdx.x;
   const double inv_plane = 1.0 / plane, inv_nx = 1.0 / nx;
 
+  static_assert(MAXE <= 64, "wall flags are kept in one 64-bit mask");
   double vals[MAXE];                              // S^gamma: gather the slab
-  unsigned wall = 0;
+  unsigned long long wall = 0;
 #pragma unroll
   for (int i = 0; i < MAXE; ++i) {
     const int e = min(t + kAC * i, tot - 1);
     const int zl = qdiv(e, inv_plane), rem = e - zl * plane;
     const int y = qdiv(rem, inv_nx), x = rem - y * nx;
-    if (box_wall(q, x, y, z0 + zl)) wall |= 1u << i;
+    if (box_wall(q, x, y, z0 + zl)) wall |= 1ull << i;
     vals[i] = src[((B.bz0 + z0 + zl) * D.ny + (B.by0 + y)) * D.nx + (B.bx0 + x)];
   }
 #pragma unroll
   for (int i = 0; i < MAXE; ++i) {
     const int e = t + kAC * i;
-    if (e < tot) buf[e] = ((wall >> i) & 1u) ? T(0) : (T)vals[i];
+    if (e < tot) buf[e] = ((wall >> i) & 1ull) ? T(0) : (T)vals[i];
   }
   __syncthreads();
 

@@ -100,6 +100,9 @@ def test_stencil_two_domains():
     (48, 16, 8.0, 8, 1),               # 27 boxes of sides {17, 18}
     (24, 8, 2.0, 4, 2),                # overlap 2, boxes {10, 12}
     (16, 0, 0.5, 0, 1),                # one box = the whole domain (C1 shape)
+    (96, 32, 2.0, 8, 3),               # size class 40: boxes {35, 38}
+    (102, 34, 2.0, 6, 3),              # size class 40: boxes {37, 40}
+    (84, 42, 8.0, 4, 3),               # size class 48: boxes of 45
 ])
 def test_precond_fp64_matches_oracle(n, sub, c, blk, overlap):
     P = problem(n, sub, c, blk, seed=n + sub)
@@ -134,18 +137,24 @@ def rel2(a, b):
 # table entries (unit roundoff u: 2^-24 FP32, 2^-8 bf16), so each stage adds a
 # 2-norm relative error of at most about 2u (the transforms are orthogonal and
 # the 3x3 solve is a contraction, ||B^-1|| <= 1).  Bound: 12u.
+@pytest.mark.parametrize("n,sub,blk,overlap", [
+    (48, 16, 8, 1),                    # size class 24
+    (96, 32, 8, 3),                    # size class 40
+    (84, 42, 4, 3),                    # size class 48
+])
 @pytest.mark.parametrize("precision,u", [("fp32", 2.0**-24), ("bf16", 2.0**-8)])
-def test_precond_reduced_precision_error_bound(precision, u):
-    P = problem(48, 16, 2.0, 8, seed=7)
-    h = handle_for(P, precision=precision)
+def test_precond_reduced_precision_error_bound(precision, u, n, sub, blk, overlap):
+    P = problem(n, sub, 2.0, blk, seed=7)
+    h = handle_for(P, precision=precision, overlap=overlap)
     z = h.new_vector()
     h.apply_precond(dev(P["rhs"]), z)
-    ref = ras.ras_apply(P["rhs"], 2.0, P["sub"], 1, eps_cell_of(P))
+    ref = ras.ras_apply(P["rhs"], 2.0, P["sub"], overlap, eps_cell_of(P))
     out = host(z, ref.shape)
     err = rel2(out, ref)
-    print(f"{precision}: 2-norm rel err {err:.3e} (bound {12 * u:.3e})")
+    print(f"{precision} n={n} sub={sub} overlap={overlap}: 2-norm rel err {err:.3e} "
+          f"(bound {12 * u:.3e})")
     assert err < 12 * u
-    assert np.all(out[~inputs.unknown_slots(48, 48, 48)] == 0.0)
+    assert np.all(out[~inputs.unknown_slots(n, n, n)] == 0.0)
 
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
