@@ -275,6 +275,57 @@ def convergence_leg(args, dev, log):
                 rows=rows)
 
 
+def cn_leg(args, dev, log):
+    """Crank-Nicolson time stepping around the solve (Sec. II-A, eqs. (2)-(5))
+    on the 256^3 medium of the main workload: E^0 = N(0,1) (seed 21), H^0 = 0,
+    dt = 2 sqrt(c) = 2 sqrt(2); each step builds R, solves A E+ = R by FP64
+    FGMRES(30) with the FP64 RAS to 1e-8 of the warm-start residual, and
+    updates H.  Reports time per step, iterations and the drift of the
+    discrete energy (1/2)(E^T eps E + H^T H), which Crank-Nicolson conserves
+    up to the solve tolerance."""
+    import torch
+    from paper_2508_07193_amd import api, inputs
+    P = inputs.make_problem(args.config)
+    n, blk = P["nx"], P["eps_block"]
+    h = api.Handle([dict(nx=n, ny=n, nz=n, c=P["c"], eps=P["eps"], eps_block=blk, sub=P["sub"])],
+                   precision="fp64", device=dev)
+    cell = torch.from_numpy(P["eps"]).to(dev)
+    for ax in range(3):
+        cell = cell.repeat_interleave(blk, dim=ax)
+    ee = torch.zeros(3, n, n, n, dtype=torch.float64, device=dev)      # edge eps, padded
+    ee[0, 1:, 1:, :] = 0.25 * (((cell[:-1, :-1, :] + cell[1:, :-1, :]) + cell[:-1, 1:, :]) + cell[1:, 1:, :])
+    ee[1, 1:, :, 1:] = 0.25 * (((cell[:-1, :, :-1] + cell[1:, :, :-1]) + cell[:-1, :, 1:]) + cell[1:, :, 1:])
+    ee[2, :, 1:, 1:] = 0.25 * (((cell[:, :-1, :-1] + cell[:, 1:, :-1]) + cell[:, :-1, 1:]) + cell[:, 1:, 1:])
+    ee = ee.reshape(-1)
+    del cell
+    E = torch.from_numpy(inputs.normal_rhs(np.random.default_rng(21), n, n, n).ravel()).to(dev)
+    H = h.new_vector()
+
+    def energy():
+        return 0.5 * float(torch.dot(ee * E, E) + torch.dot(H, H))
+
+    W0 = energy()
+    kw = dict(solver="fgmres", rtol=1e-8, max_iter=300)
+    h.cn_step(E, H, **kw)                                # warm-up step (not timed)
+    steps, its, drift = max(3, args.steps), [], []
+    W = energy()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        info = h.cn_step(E, H, **kw)
+        its.append(info["iterations"])
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    W1 = energy()
+    log(f"[cn] {steps} steps, {ms:.2f} ms/step, iterations {its}, energy {W0:.6e} -> {W:.6e} -> {W1:.6e}")
+    return dict(workload="256^3 Yee grid, PEC walls, eps_r U[1,10] on 8^3 cubes, c=2 (dt = 2 sqrt(2)), "
+                         "E0 N(0,1) seed 21, H0 = 0; FP64 FGMRES(30) + FP64 RAS to 1e-8 of the "
+                         "warm-start residual per step",
+                steps_timed=steps, ms_per_step=round(ms, 2), iterations_per_step=its,
+                energy_rel_drift_per_step=abs(W1 - W) / W / steps,
+                energy_rel_drift_total=abs(W1 - W0) / W0)
+
+
 def c3_context(args):
     """Problem, device vectors and timing helpers of the 256^3 legs (child process)."""
     import torch
@@ -440,6 +491,8 @@ def run_leg(args):
         res = learned_leg(args, dev, log)
     elif args.leg == "convergence":
         res = convergence_leg(args, dev, log)
+    elif args.leg == "cn":
+        res = cn_leg(args, dev, log)
     else:
         raise SystemExit(f"unknown leg {args.leg}")
     print("LEG_RESULT " + json.dumps(res), flush=True)
@@ -471,6 +524,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--learned", type=int, default=1, help="run the C5 learned-correction leg")
     ap.add_argument("--batch", type=int, default=1, help="run the 64-domain batch leg")
+    ap.add_argument("--cn", type=int, default=1,
+                    help="run the Crank-Nicolson time-stepping leg (256^3)")
     ap.add_argument("--convergence", type=int, default=1,
                     help="run the overlap / solver convergence study leg (128^3)")
     ap.add_argument("--pairs-rhs", type=int, default=100)
@@ -513,6 +568,8 @@ def main():
             out["variants"]["learned_c5"] = child(args, "learned")
         if args.convergence:
             out["variants"]["convergence_overlap"] = child(args, "convergence")
+        if args.cn:
+            out["variants"]["cn_time_stepping"] = child(args, "cn")
     finally:
         shutil.rmtree(tmp, ignore_errors=True)
     if not args.no_cpu:

@@ -213,6 +213,46 @@ fmp_status fmp_solve_workspace(fmp_handle h, const fmp_solve_opts* opts, size_t*
 fmp_status fmp_solve(fmp_handle h, const double* b, double* x, const fmp_solve_opts* opts,
                      void* ws, size_t ws_bytes, fmp_solve_info* info, void* stream);
 
+/* ---- Crank-Nicolson time stepping around the solve ---------------------------
+ * Sec. II-A, eqs. (2)-(5): Maxwell's curl equations in normalised units
+ * (mu = 1, unit cell size, eps the relative permittivity) marched by
+ * Crank-Nicolson,
+ *     eps (E+ - E) / dt =  (1/2) C^T (H+ + H),   (H+ - H) / dt = -(1/2) C (E+ + E),
+ * C the Yee curl from E (edges) to H (dual faces) of Sec. III-A eq. (6).
+ * Eliminating H+ gives A E+ = R with A the operator of fmp_curlcurl_apply,
+ * c = dt^2 / 4 and R = E + dt eps^-1 C^T (H - (dt/4) C E); so a domain's time
+ * step is dt = 2 sqrt(c) (its fmp_domain_desc.c).
+ * H vectors have the E layout (fmp_vector_layout): per domain [3][nz][ny][nx],
+ * H_x at (i, j+1/2, k+1/2) in slot [k][j][i], H_y at (i+1/2, j, k+1/2),
+ * H_z at (i+1/2, j+1/2, k); slot 0 of a component's own axis (i for H_x, j for
+ * H_y, k for H_z) is a wall slot, ignored on input and 0 on output. */
+
+/* h_out = beta h_in + m dt C (e1 + e2), each domain with its own dt.
+ * e2 and h_in may be NULL (taken as zero).  Device vectors of the layout
+ * length; h_out may be h_in itself, must not overlap e1 or e2
+ * (FMP_ERR_ALIAS).  Wall slots of e1, e2, h_in are ignored. */
+fmp_status fmp_curl_e(fmp_handle h, const double* e1, const double* e2, const double* h_in,
+                      double beta, double m, double* h_out, void* stream);
+
+/* e_out = e_in + m dt eps_e^-1 C^T hf, eps_e the edge permittivity of the
+ * operator A (mean of the four cells sharing the edge).  e_in may be NULL
+ * (zero) or e_out itself; hf must not overlap e_out (FMP_ERR_ALIAS). */
+fmp_status fmp_curl_h(fmp_handle h, const double* hf, const double* e_in, double m,
+                      double* e_out, void* stream);
+
+/* Workspace of fmp_cn_step for opts (bytes): the solver's plus two vectors. */
+fmp_status fmp_cn_workspace(fmp_handle h, const fmp_solve_opts* opts, size_t* bytes);
+
+/* One Crank-Nicolson step in place: R = E + dt eps^-1 C^T (H - (dt/4) C E);
+ * A E+ = R by fmp_solve with opts, started from E (so rtol is relative to the
+ * initial residual b - A E); H = H - (dt/2) C (E+ + E); E = E+.  E, H: device,
+ * layout length, not overlapping; ws: device buffer of fmp_cn_workspace bytes
+ * (256-byte aligned).  Returns fmp_solve's status; on a status other than
+ * FMP_OK and FMP_NOT_CONVERGED, E and H are unchanged.  Synchronises the
+ * stream.  info may be NULL. */
+fmp_status fmp_cn_step(fmp_handle h, double* E, double* H, const fmp_solve_opts* opts, void* ws,
+                       size_t ws_bytes, fmp_solve_info* info, void* stream);
+
 /* ---- learned coarse correction (z += P0 MLP(R0 r)) --------------------------
  * R0: mean of r over the unknowns each subdomain owns, per component; the
  * coarse vector is [3][n_subdomains] (subdomains in the same order as the

@@ -12,7 +12,8 @@ PRECISION = {"fp64": 0, "fp32": 1, "bf16": 2}
 
 # every symbol include/flashmp.h declares
 EXPORTS = ["fmp_setup_subdomains", "fmp_vector_layout", "fmp_curlcurl_apply", "fmp_apply_precond",
-           "fmp_autotune", "fmp_solve_workspace", "fmp_solve", "fmp_coarse_size", "fmp_set_coarse_model",
+           "fmp_autotune", "fmp_solve_workspace", "fmp_solve", "fmp_curl_e", "fmp_curl_h",
+           "fmp_cn_workspace", "fmp_cn_step", "fmp_coarse_size", "fmp_set_coarse_model",
            "fmp_coarse_restrict", "fmp_mlp_loss_grad", "fmp_mlp_scratch_bytes", "fmp_mlp_adam",
            "fmp_destroy", "fmp_status_string", "fmp_last_error"]
 
@@ -71,6 +72,11 @@ def load():
     L.fmp_autotune.argtypes = [vp, vp, vp, C.POINTER(TuneEntry), i32, C.POINTER(i32), vp]
     L.fmp_solve_workspace.argtypes = [vp, C.POINTER(SolveOpts), C.POINTER(sz)]
     L.fmp_solve.argtypes = [vp, vp, vp, C.POINTER(SolveOpts), vp, sz, C.POINTER(SolveInfo), vp]
+    f8 = C.c_double
+    L.fmp_curl_e.argtypes = [vp, vp, vp, vp, f8, f8, vp, vp]
+    L.fmp_curl_h.argtypes = [vp, vp, vp, f8, vp, vp]
+    L.fmp_cn_workspace.argtypes = [vp, C.POINTER(SolveOpts), C.POINTER(sz)]
+    L.fmp_cn_step.argtypes = [vp, vp, vp, C.POINTER(SolveOpts), vp, sz, C.POINTER(SolveInfo), vp]
     L.fmp_coarse_size.argtypes = [vp, C.POINTER(i32)]
     L.fmp_set_coarse_model.argtypes = [vp, i32, C.POINTER(C.c_float), sz]
     L.fmp_coarse_restrict.argtypes = [vp, vp, vp, vp]

@@ -91,6 +91,7 @@ class Handle:
         self.offsets = [int(o) for o in offs]
         self.length = self.offsets[-1]
         self._solve_ws = None
+        self._cn_ws = None
 
     def close(self):
         if self.h is not None and self.h.value:
@@ -117,6 +118,15 @@ class Handle:
 
     def solve(self, b, x, **kw):
         return fmp_solve(self, b, x, **kw)
+
+    def curl_e(self, e1, h_out, e2=None, h_in=None, beta=0.0, m=1.0, stream=None):
+        return fmp_curl_e(self, e1, h_out, e2, h_in, beta, m, stream)
+
+    def curl_h(self, hf, e_out, e_in=None, m=1.0, stream=None):
+        return fmp_curl_h(self, hf, e_out, e_in, m, stream)
+
+    def cn_step(self, E, H, **kw):
+        return fmp_cn_step(self, E, H, **kw)
 
 
 def fmp_setup_subdomains(domains, **kw):
@@ -190,6 +200,36 @@ def fmp_solve(h, b, x, stream=None, raise_on_breakdown=True, **kw):
                    bytes_orth_dot=info.bytes_orth_dot, bytes_orth_update=info.bytes_orth_update,
                    n_orth_dot=info.n_orth_dot, n_orth_update=info.n_orth_update)
     return out
+
+
+def fmp_curl_e(h, e1, h_out, e2=None, h_in=None, beta=0.0, m=1.0, stream=None):
+    """h_out = beta h_in + m dt C (e1 + e2) per domain, dt = 2 sqrt(c)."""
+    _check(_lib.load().fmp_curl_e(h.h, _ptr(e1), _ptr(e2) if e2 is not None else None,
+                                  _ptr(h_in) if h_in is not None else None, float(beta), float(m),
+                                  _ptr(h_out), _stream(stream)), "fmp_curl_e", h.h)
+
+
+def fmp_curl_h(h, hf, e_out, e_in=None, m=1.0, stream=None):
+    """e_out = e_in + m dt eps_e^-1 C^T hf per domain, dt = 2 sqrt(c)."""
+    _check(_lib.load().fmp_curl_h(h.h, _ptr(hf), _ptr(e_in) if e_in is not None else None,
+                                  float(m), _ptr(e_out), _stream(stream)), "fmp_curl_h", h.h)
+
+
+def fmp_cn_step(h, E, H, stream=None, **kw):
+    """One Crank-Nicolson step of (E, H) in place; returns the solve's statistics."""
+    L = _lib.load()
+    o = solve_opts(**kw)
+    nbytes = C.c_size_t(0)
+    _check(L.fmp_cn_workspace(h.h, C.byref(o), C.byref(nbytes)), "fmp_cn_workspace", h.h)
+    if h._cn_ws is None or h._cn_ws.numel() < nbytes.value:
+        h._cn_ws = None
+        h._cn_ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=h.device)
+    info = _lib.SolveInfo()
+    st = L.fmp_cn_step(h.h, _ptr(E), _ptr(H), C.byref(o), _ptr(h._cn_ws), nbytes.value,
+                       C.byref(info), _stream(stream))
+    _check(st, "fmp_cn_step", h.h, ok=(0, 1))
+    return dict(status=_lib.STATUS[st], iterations=info.iterations,
+                rel_residual_true=info.rel_residual_true, t_total_ms=info.t_total_ms)
 
 
 def release_solver_workspace(h):

@@ -1,0 +1,157 @@
+"""Crank-Nicolson time stepping (Sec. II-A, eqs. (2)-(5)) on the GPU path,
+through the C ABI, against the oracle (oracle/fdtd.py).
+
+The curls are integer-weight differences: with integer fields and a unit
+scale (c = 1/4, dt = 1) both sides are exact, so the comparison is bitwise.
+With a permittivity each edge value is one division and one multiply away
+from exact (1e-14 relative).  A time step solves A E+ = R iteratively to
+1e-12 of the warm-start residual (A has condition number <= 1 + 12 c), so
+E+ and H+ agree with the oracle's direct solve to 1e-9 relative.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import fdtd, transforms, yee
+from paper_2508_07193_amd import api, inputs
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64).ravel()).to(DEV)
+
+
+def host(t, shape):
+    torch.cuda.synchronize()
+    return t.cpu().numpy().reshape(shape)
+
+
+def with_garbage(v, mask, value=77.0):
+    return np.where(mask, v, value)
+
+
+def test_curl_e_integer_bitwise():
+    nx, ny, nz = 70, 10, 19
+    rng = np.random.default_rng(0)
+    C = yee.curl_matrix(nx, ny, nz)
+    e1 = rng.integers(-8, 9, yee.n_unknowns(nx, ny, nz)).astype(float)
+    e2 = rng.integers(-8, 9, yee.n_unknowns(nx, ny, nz)).astype(float)
+    hin = rng.integers(-8, 9, C.shape[0]).astype(float)
+    emask, hmask = yee.wall_mask(nx, ny, nz), fdtd.h_mask(nx, ny, nz)
+    h = api.Handle([dict(nx=nx, ny=ny, nz=nz, c=0.25)], device=DEV)   # dt = 1
+    out = h.new_vector()
+    h.curl_e(dev(with_garbage(yee.to_padded(e1, nx, ny, nz), emask)), out)
+    ref = fdtd.h_to_padded(C @ e1, nx, ny, nz)
+    assert np.array_equal(host(out, ref.shape), ref)
+    h.curl_e(dev(with_garbage(yee.to_padded(e1, nx, ny, nz), emask)), out,
+             e2=dev(with_garbage(yee.to_padded(e2, nx, ny, nz), emask)),
+             h_in=dev(with_garbage(fdtd.h_to_padded(hin, nx, ny, nz), hmask)), beta=2.0, m=-3.0)
+    ref = fdtd.h_to_padded(2.0 * hin - 3.0 * (C @ (e1 + e2)), nx, ny, nz)
+    assert np.array_equal(host(out, ref.shape), ref)
+
+
+def test_curl_h_integer_bitwise():
+    nx, ny, nz = 33, 21, 9
+    rng = np.random.default_rng(1)
+    C = yee.curl_matrix(nx, ny, nz)
+    hf = rng.integers(-8, 9, C.shape[0]).astype(float)
+    ein = rng.integers(-8, 9, yee.n_unknowns(nx, ny, nz)).astype(float)
+    h = api.Handle([dict(nx=nx, ny=ny, nz=nz, c=0.25)], device=DEV)
+    out = h.new_vector()
+    h.curl_h(dev(with_garbage(fdtd.h_to_padded(hf, nx, ny, nz), fdtd.h_mask(nx, ny, nz))), out,
+             e_in=dev(with_garbage(yee.to_padded(ein, nx, ny, nz), yee.wall_mask(nx, ny, nz))))
+    ref = yee.to_padded(ein + C.T @ hf, nx, ny, nz)
+    assert np.array_equal(host(out, ref.shape), ref)
+
+
+def test_curl_h_with_permittivity():
+    nx, ny, nz, blk, c = 24, 16, 20, 4, 2.0
+    rng = np.random.default_rng(2)
+    eps = inputs.eps_table(rng, nx, ny, nz, blk)
+    eps_cell = yee.expand_eps(eps, blk, nx, ny, nz)
+    C = yee.curl_matrix(nx, ny, nz)
+    hf = rng.standard_normal(C.shape[0])
+    ein = rng.standard_normal(yee.n_unknowns(nx, ny, nz))
+    h = api.Handle([dict(nx=nx, ny=ny, nz=nz, c=c, eps=eps, eps_block=blk)], device=DEV)
+    e = dev(yee.to_padded(ein, nx, ny, nz))
+    h.curl_h(dev(fdtd.h_to_padded(hf, nx, ny, nz)), e, e_in=e, m=0.5)     # in place
+    dt = fdtd.time_step(c)
+    ref = yee.to_padded(ein + (0.5 * dt / yee.edge_eps(eps_cell)) * (C.T @ hf), nx, ny, nz)
+    out = host(e, ref.shape)
+    assert np.abs(out - ref).max() <= 1e-14 * np.abs(ref).max()
+
+
+def _cn_case(nx, ny, nz, sub, blk, c, seed):
+    rng = np.random.default_rng(seed)
+    eps = inputs.eps_table(rng, nx, ny, nz, blk) if blk else None
+    eps_cell = yee.expand_eps(eps, blk, nx, ny, nz) if blk else None
+    E = rng.standard_normal(yee.n_unknowns(nx, ny, nz))
+    H = rng.standard_normal(yee.curl_matrix(nx, ny, nz).shape[0])
+    dom = dict(nx=nx, ny=ny, nz=nz, c=c, sub=sub)
+    if blk:
+        dom.update(eps=eps, eps_block=blk)
+    return dom, eps_cell, E, H
+
+
+@pytest.mark.parametrize("solver", ["bicgstab", "fgmres"])
+def test_cn_steps_match_oracle_and_conserve_energy(solver):
+    nx, ny, nz = 24, 16, 20
+    dom, eps_cell, E0, H0 = _cn_case(nx, ny, nz, (12, 8, 10), 4, 2.0, 3)
+    h = api.Handle([dom], device=DEV)
+    E = dev(with_garbage(yee.to_padded(E0, nx, ny, nz), yee.wall_mask(nx, ny, nz)))
+    H = dev(with_garbage(fdtd.h_to_padded(H0, nx, ny, nz), fdtd.h_mask(nx, ny, nz)))
+    Eo, Ho = E0.copy(), H0.copy()
+    eps_e = yee.edge_eps(eps_cell)
+    W0 = fdtd.energy(E0, H0, eps_e)
+    for _ in range(3):
+        info = h.cn_step(E, H, solver=solver, rtol=1e-12, max_iter=200)
+        assert info["status"] == "FMP_OK", info
+        Eo, Ho = fdtd.cn_step(Eo, Ho, nx, ny, nz, 2.0, eps_cell)
+        Eg = host(E, (3, nz, ny, nx))
+        Hg = host(H, (3, nz, ny, nx))
+        assert np.all(Eg[~yee.wall_mask(nx, ny, nz)] == 0.0)
+        assert np.all(Hg[~fdtd.h_mask(nx, ny, nz)] == 0.0)
+        e, hh = yee.from_padded(Eg), fdtd.h_from_padded(Hg)
+        assert np.abs(e - Eo).max() <= 1e-9 * np.abs(Eo).max()
+        assert np.abs(hh - Ho).max() <= 1e-9 * np.abs(Ho).max()
+        assert abs(fdtd.energy(e, hh, eps_e) - W0) <= 1e-9 * W0
+
+
+def test_cn_two_domains_take_their_own_time_step():
+    cases = [_cn_case(16, 16, 16, (8, 8, 8), 0, 0.5, 4), _cn_case(20, 12, 16, (10, 6, 8), 4, 3.0, 5)]
+    h = api.Handle([d for d, _, _, _ in cases], device=DEV)
+    E = torch.cat([dev(yee.to_padded(e, d["nx"], d["ny"], d["nz"])) for d, _, e, _ in cases])
+    H = torch.cat([dev(fdtd.h_to_padded(hh, d["nx"], d["ny"], d["nz"])) for d, _, _, hh in cases])
+    info = h.cn_step(E, H, solver="fgmres", rtol=1e-12, max_iter=200)
+    assert info["status"] == "FMP_OK", info
+    for k, (d, eps_cell, e0, h0) in enumerate(cases):
+        nx, ny, nz = d["nx"], d["ny"], d["nz"]
+        a, b = h.offsets[k], h.offsets[k + 1]
+        Eg = E[a:b].cpu().numpy().reshape(3, nz, ny, nx)
+        Hg = H[a:b].cpu().numpy().reshape(3, nz, ny, nx)
+        Eo, Ho = fdtd.cn_step(e0, h0, nx, ny, nz, d["c"], eps_cell)
+        assert np.abs(yee.from_padded(Eg) - Eo).max() <= 1e-9 * np.abs(Eo).max()
+        assert np.abs(fdtd.h_from_padded(Hg) - Ho).max() <= 1e-9 * np.abs(Ho).max()
+
+
+def test_cn_cavity_mode_turns_by_the_cn_angle():
+    n, c = 32, 1.5
+    p, q, r = 3, 5, 2
+    s = np.array([transforms.sigma(n)[p], transforms.sigma(n)[q], transforms.sigma(n)[r]])
+    lam = float(s @ s)
+    spec = np.zeros((3, n, n, n))
+    spec[:, r, q, p] = np.cross(s, [1.0, 0.2, -0.5])
+    E0 = transforms.inverse_G(spec, n, n, n)
+    E0 /= np.abs(E0).max()
+    C = yee.curl_matrix(n, n, n)
+    theta = 2.0 * np.arctan(fdtd.time_step(c) * np.sqrt(lam) / 2.0)
+    h = api.Handle([dict(nx=n, ny=n, nz=n, c=c, sub=(16, 16, 16))], device=DEV)
+    E, H = dev(yee.to_padded(E0, n, n, n)), h.new_vector()
+    for k in range(1, 5):
+        h.cn_step(E, H, solver="bicgstab", rtol=1e-12, max_iter=100)
+        e = yee.from_padded(host(E, (3, n, n, n)))
+        hh = fdtd.h_from_padded(host(H, (3, n, n, n)))
+        assert np.abs(e - np.cos(k * theta) * E0).max() <= 1e-9
+        assert np.abs(hh + np.sin(k * theta) * (C @ E0) / np.sqrt(lam)).max() <= 1e-9
