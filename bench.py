@@ -32,11 +32,11 @@ HBM_PEAK_GBS = 8000.0
 # since, traffic is null.
 TRAFFIC = {
     "k_mupdate": (1.0000, {"fmp_krylov.hip": "f1f24bd32b8cc02cdd320efeebc215ced08006197fdf91b76559306a267737d5",
-                          "fmp_common.h": "0150c906c8e7097f7526eb2705dbd6e634fed83d49309e950b57f50d8ba7bb17"}),
+                          "fmp_common.h": "4b12919ac40ea6352d4233abf1f834b5a53a20f2fd05c1e70c910735a7dc8db7"}),
     "k_mdot": (1.0000, {"fmp_krylov.hip": "f1f24bd32b8cc02cdd320efeebc215ced08006197fdf91b76559306a267737d5",
-                          "fmp_common.h": "0150c906c8e7097f7526eb2705dbd6e634fed83d49309e950b57f50d8ba7bb17"}),
-    "k_curlcurl": (1.0720, {"fmp_stencil.hip": "de1405a66a1406a29665d8febfe02f57f73061b26dfc1278dde215ed059136fb",
-                          "fmp_common.h": "0150c906c8e7097f7526eb2705dbd6e634fed83d49309e950b57f50d8ba7bb17"}),
+                          "fmp_common.h": "4b12919ac40ea6352d4233abf1f834b5a53a20f2fd05c1e70c910735a7dc8db7"}),
+    "k_curlcurl": (1.0365, {"fmp_stencil.hip": "7fd7ff0c4eba81bdabfa8cbe6fb11d031c2ed4066c6f3f3a160de218c3ec3b12",
+                          "fmp_common.h": "4b12919ac40ea6352d4233abf1f834b5a53a20f2fd05c1e70c910735a7dc8db7"}),
 }
 
 

@@ -88,21 +88,31 @@ __global__ __launch_bounds__(kFX * kFY) void k_curl_h(const double* __restrict__
   const double cx = (hz - H(2, k, j - 1, i)) - (hy - H(1, k - 1, j, i));
   const double cy = (hx - H(0, k - 1, j, i)) - (hz - H(2, k, j, i - 1));
   const double cz = (hy - H(1, k, j, i - 1)) - (hx - H(0, k, j - 1, i));
-  // cell permittivity, indices clamped into the domain (wall slots only)
-  auto cell = [&](int kk, int jj, int ii) -> double {
-    if (D.eps_b <= 0) return 1.0;
-    const int b = D.eps_b;
-    kk = min(max(kk, 0), nz - 1);
-    jj = min(max(jj, 0), ny - 1);
-    ii = min(max(ii, 0), nx - 1);
-    return eps[D.eps_off + ((kk / b) * D.eps_nby + (jj / b)) * D.eps_nbx + (ii / b)];
-  };
-  const double ex_e = 0.25 * (((cell(k - 1, j - 1, i) + cell(k, j - 1, i)) + cell(k - 1, j, i)) +
-                              cell(k, j, i));
-  const double ey_e = 0.25 * (((cell(k - 1, j, i - 1) + cell(k, j, i - 1)) + cell(k - 1, j, i)) +
-                              cell(k, j, i));
-  const double ez_e = 0.25 * (((cell(k, j - 1, i - 1) + cell(k, j, i - 1)) + cell(k, j - 1, i)) +
-                              cell(k, j, i));
+  // cells c[dk][dj][di] at (k-1+dk, j-1+dj, i-1+di) (c000 is not needed), clamped
+  // into the domain (only wall slots reach outside); eps cube indices from an
+  // exact float quotient (v < 2^22)
+  double c001 = 1.0, c010 = 1.0, c011 = 1.0, c100 = 1.0, c101 = 1.0, c110 = 1.0, c111 = 1.0;
+  if (D.eps_b > 0) {
+    const float inv_b = 1.f / (float)D.eps_b;
+    auto blk = [&](int v, int n) { return (int)(((float)min(max(v, 0), n - 1) + 0.5f) * inv_b); };
+    const int kb0 = blk(k - 1, nz), kb1 = blk(k, nz);
+    const int jb0 = blk(j - 1, ny), jb1 = blk(j, ny);
+    const int ib0 = blk(i - 1, nx), ib1 = blk(i, nx);
+    const double* et = eps + D.eps_off;
+    auto at = [&](int kb, int jb, int ib) { return et[((long long)kb * D.eps_nby + jb) * D.eps_nbx + ib]; };
+    c001 = at(kb0, jb0, ib1);
+    c010 = at(kb0, jb1, ib0);
+    c011 = at(kb0, jb1, ib1);
+    c100 = at(kb1, jb0, ib0);
+    c101 = at(kb1, jb0, ib1);
+    c110 = at(kb1, jb1, ib0);
+    c111 = at(kb1, jb1, ib1);
+  }
+  // edge permittivity: mean of the four cells sharing the edge, in the order
+  // (-,-), (+,-), (-,+), (+,+) of the two transverse axes
+  const double ex_e = 0.25 * (((c001 + c101) + c011) + c111);
+  const double ey_e = 0.25 * (((c010 + c110) + c011) + c111);
+  const double ez_e = 0.25 * (((c100 + c110) + c101) + c111);
   const long long o = D.offset + ((long long)k * ny + j) * nx + i;
   const double cv[3] = {cx, cy, cz}, ev[3] = {ex_e, ey_e, ez_e};
 #pragma unroll
