@@ -102,12 +102,17 @@ __global__ __launch_bounds__(kThreads) void k_mdot(const double* __restrict__ V,
     seg_walk2(
         sg,
         [&](long long p) {
-          const dbl2 we = w2[p];
+          // all loads of the step are issued before the first product: the
+          // compiler would otherwise consume each basis vector as it arrives
+          // and keep only two or three loads in flight per wave
+          dbl2 vv[NV];
 #pragma unroll
-          for (int i = 0; i < NV; ++i) {
-            const dbl2 v = ld_stream(V + i * ldv, p);
-            acc[i] = __builtin_fma(v.x, we.x, __builtin_fma(v.y, we.y, acc[i]));
-          }
+          for (int i = 0; i < NV; ++i) vv[i] = ld_stream(V + i * ldv, p);
+          const dbl2 we = w2[p];
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int i = 0; i < NV; ++i)
+            acc[i] = __builtin_fma(vv[i].x, we.x, __builtin_fma(vv[i].y, we.y, acc[i]));
           acc[NV] = __builtin_fma(we.x, we.x, __builtin_fma(we.y, we.y, acc[NV]));
         },
         [&](long long e) {
