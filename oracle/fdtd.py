@@ -94,3 +94,46 @@ def cn_step(E, H, nx, ny, nz, c, eps_cell=None):
 def energy(E, H, eps_e):
     """Discrete electromagnetic energy (1/2)(sum eps_e E^2 + sum H^2) (mu = 1)."""
     return 0.5 * (float(np.dot(eps_e * E, E)) + float(np.dot(H, H)))
+
+
+def _window(a, n):
+    return max(0, a - 2), min(n, a + 3)
+
+
+def curl_e_at(e_pad, points):
+    """(C E) at selected padded H slots, for checks on grids too large to assemble.
+
+    Each value comes from a window of up to 5 cells per axis around the slot,
+    assembled as its own PEC domain (yee.curl_matrix): the face curl of the
+    centre slot reads E at its own index and one above, both inside the
+    window, so the window's own walls never enter it."""
+    _, nz, ny, nx = e_pad.shape
+    out = []
+    for (q, k, j, i) in points:
+        (x0, x1), (y0, y1), (z0, z1) = _window(i, nx), _window(j, ny), _window(k, nz)
+        sub = e_pad[:, z0:z1, y0:y1, x0:x1] * yee.wall_mask(x1 - x0, y1 - y0, z1 - z0)
+        C = yee.curl_matrix(x1 - x0, y1 - y0, z1 - z0)
+        hw = h_to_padded(C @ yee.from_padded(sub), x1 - x0, y1 - y0, z1 - z0)
+        out.append(hw[q, k - z0, j - y0, i - x0])
+    return np.array(out)
+
+
+def curl_h_at(h_pad, eps_cell, points):
+    """(C^T H) and the edge permittivity at selected padded E slots (same
+    window construction; the edge curl reads H at its own index and one
+    below, and the four cells around the edge)."""
+    _, nz, ny, nx = h_pad.shape
+    ct, ee = [], []
+    for (q, k, j, i) in points:
+        (x0, x1), (y0, y1), (z0, z1) = _window(i, nx), _window(j, ny), _window(k, nz)
+        wnx, wny, wnz = x1 - x0, y1 - y0, z1 - z0
+        sub = h_pad[:, z0:z1, y0:y1, x0:x1] * h_mask(wnx, wny, wnz)
+        C = yee.curl_matrix(wnx, wny, wnz)
+        ew = yee.to_padded(C.T @ h_from_padded(sub), wnx, wny, wnz)
+        ct.append(ew[q, k - z0, j - y0, i - x0])
+        if eps_cell is None:
+            ee.append(1.0)
+        else:
+            e_e = yee.to_padded(yee.edge_eps(eps_cell[z0:z1, y0:y1, x0:x1]), wnx, wny, wnz)
+            ee.append(e_e[q, k - z0, j - y0, i - x0])
+    return np.array(ct), np.array(ee)

@@ -155,3 +155,72 @@ def test_cn_cavity_mode_turns_by_the_cn_angle():
         hh = fdtd.h_from_padded(host(H, (3, n, n, n)))
         assert np.abs(e - np.cos(k * theta) * E0).max() <= 1e-9
         assert np.abs(hh + np.sin(k * theta) * (C @ E0) / np.sqrt(lam)).max() <= 1e-9
+
+
+def test_minimal_domain_step_matches_oracle():
+    """2 x 2 x 3 cells: one box, a single interior node per transverse axis."""
+    nx, ny, nz, c = 2, 2, 3, 0.7
+    rng = np.random.default_rng(9)
+    E0 = rng.standard_normal(yee.n_unknowns(nx, ny, nz))
+    H0 = rng.standard_normal(yee.curl_matrix(nx, ny, nz).shape[0])
+    h = api.Handle([dict(nx=nx, ny=ny, nz=nz, c=c)], device=DEV)
+    E, H = dev(yee.to_padded(E0, nx, ny, nz)), dev(fdtd.h_to_padded(H0, nx, ny, nz))
+    info = h.cn_step(E, H, solver="bicgstab", rtol=1e-13, max_iter=50)
+    assert info["status"] == "FMP_OK", info
+    Eo, Ho = fdtd.cn_step(E0, H0, nx, ny, nz, c)
+    assert np.abs(yee.from_padded(host(E, (3, nz, ny, nx))) - Eo).max() <= 1e-11
+    assert np.abs(fdtd.h_from_padded(host(H, (3, nz, ny, nx))) - Ho).max() <= 1e-11
+
+
+def test_curl_and_step_error_paths():
+    nx, ny, nz = 8, 8, 8
+    h = api.Handle([dict(nx=nx, ny=ny, nz=nz, c=1.0, sub=(4, 4, 4))], device=DEV)
+    a, b = h.new_vector(), h.new_vector()
+    a.normal_()
+    with pytest.raises(api.FlashMPError, match="ALIAS"):
+        h.curl_e(a, a)                                # h_out overlaps e1
+    with pytest.raises(api.FlashMPError, match="ALIAS"):
+        h.curl_h(a, a)                                # e_out overlaps hf
+    with pytest.raises(api.FlashMPError, match="ALIAS"):
+        h.cn_step(a, a)                               # E and H overlap
+    # an unconverged step still advances E and H and says so
+    E = dev(inputs.normal_rhs(np.random.default_rng(1), nx, ny, nz))
+    H = h.new_vector()
+    E_before = E.clone()
+    info = h.cn_step(E, H, solver="fgmres", rtol=1e-14, max_iter=1)
+    assert info["status"] == "FMP_NOT_CONVERGED"
+    assert not torch.equal(E, E_before) and float(torch.linalg.vector_norm(H)) > 0.0
+
+
+@pytest.mark.slow
+def test_full_256_sampled_curls():
+    """256^3 C3 medium: both curl kernels at sampled slots (walls, edges, interior)."""
+    P = inputs.make_problem("c3")
+    n, c = 256, P["c"]
+    eps_cell = yee.expand_eps(P["eps"], P["eps_block"], n, n, n)
+    rng = np.random.default_rng(4)
+    Ep = P["rhs"]
+    Hp = rng.standard_normal((3, n, n, n)) * fdtd.h_mask(n, n, n)
+    h = api.Handle([dict(nx=n, ny=n, nz=n, c=c, eps=P["eps"], eps_block=P["eps_block"],
+                         sub=P["sub"])], device=DEV)
+    E, H = dev(Ep), dev(Hp)
+    F, R = h.new_vector(), h.new_vector()
+    h.curl_e(E, F, h_in=H, beta=1.0, m=-0.25)
+    h.curl_h(H, R, e_in=E, m=1.0)
+    Fo, Ro = host(F, Ep.shape), host(R, Ep.shape)
+    dt = fdtd.time_step(c)
+    pts = [(int(q), int(k), int(j), int(i)) for q, k, j, i in
+           zip(rng.integers(0, 3, 120), rng.integers(0, n, 120), rng.integers(0, n, 120),
+               rng.integers(0, n, 120))]
+    pts += [(0, 0, 0, 1), (1, 0, 1, 0), (2, 1, 0, 0), (0, 255, 255, 255), (1, 255, 255, 255),
+            (2, 255, 255, 255), (0, 1, 1, 0), (2, 0, 255, 255)]
+    hp = [p for p in pts if fdtd.h_mask(n, n, n)[p]]
+    ep = [p for p in pts if yee.wall_mask(n, n, n)[p]]
+    ref_h = np.array([Hp[p] for p in hp]) - 0.25 * dt * fdtd.curl_e_at(Ep, hp)
+    assert np.abs(np.array([Fo[p] for p in hp]) - ref_h).max() <= 1e-13 * np.abs(Hp).max()
+    ct, ee = fdtd.curl_h_at(Hp, eps_cell, ep)
+    ref_e = np.array([Ep[p] for p in ep]) + (dt / ee) * ct
+    assert np.abs(np.array([Ro[p] for p in ep]) - ref_e).max() <= 1e-13 * np.abs(Hp).max()
+    walls_h = [p for p in pts if not fdtd.h_mask(n, n, n)[p]]
+    walls_e = [p for p in pts if not yee.wall_mask(n, n, n)[p]]
+    assert all(Fo[p] == 0.0 for p in walls_h) and all(Ro[p] == 0.0 for p in walls_e)

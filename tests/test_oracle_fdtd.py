@@ -95,3 +95,29 @@ def test_energy_is_conserved_with_permittivity():
     for _ in range(4):
         E, H = fdtd.cn_step(E, H, nx, ny, nz, c, eps)
         assert abs(fdtd.energy(E, H, eps_e) - W0) <= 1e-11 * W0
+
+
+def test_windowed_curls_match_the_assembled_operator():
+    nx, ny, nz = 9, 7, 8
+    rng = np.random.default_rng(3)
+    eps = rng.uniform(1.0, 10.0, (nz, ny, nx))
+    C = yee.curl_matrix(nx, ny, nz)
+    e = rng.standard_normal(yee.n_unknowns(nx, ny, nz))
+    hv = rng.standard_normal(C.shape[0])
+    ep, hp = yee.to_padded(e, nx, ny, nz), fdtd.h_to_padded(hv, nx, ny, nz)
+    Hf = fdtd.h_to_padded(C @ e, nx, ny, nz)
+    Ef = yee.to_padded(C.T @ hv, nx, ny, nz)
+    Ee = yee.to_padded(yee.edge_eps(eps), nx, ny, nz)
+    def sample(mask):
+        # every slot on a wall-adjacent layer, plus a seeded sample of the rest
+        pts = np.argwhere(mask)
+        edge = np.any((pts[:, 1:] <= 1) | (pts[:, 1:] >= np.array([nz, ny, nx]) - 2), axis=1)
+        rest = pts[~edge][rng.choice(int((~edge).sum()), 60, replace=False)]
+        return [tuple(int(v) for v in p) for p in np.concatenate([pts[edge][::3], rest])]
+    hpts = sample(fdtd.h_mask(nx, ny, nz))
+    epts = sample(yee.wall_mask(nx, ny, nz))
+    got = fdtd.curl_e_at(ep, hpts)
+    assert np.abs(got - np.array([Hf[p] for p in hpts])).max() < 1e-13
+    ct, ee = fdtd.curl_h_at(hp, eps, epts)
+    assert np.abs(ct - np.array([Ef[p] for p in epts])).max() < 1e-13
+    assert np.abs(ee - np.array([Ee[p] for p in epts])).max() < 1e-14
