@@ -154,21 +154,30 @@ __global__ __launch_bounds__(256) void k_mpass_a(const double* __restrict__ r, _
   bf16x8 tx[NT][KS], ty[NT][KS], a[NT][KS];
   load_tab(tx, tb + (q == 0 ? B.mdct[0] : B.mdst[0]), l16, g);
 
-  {  // S^gamma: the slab's nzs * ny * nx elements, walls as zero; loads first
+  {  // S^gamma: the slab's nzs * ny * nx elements, walls as zero; loads first.
+     // A thread's elements t + 256 i are stepped from its first one by the
+     // fixed increment of 256 elements (two carries), not decomposed anew.
     const int plane = ny * nx, tot = nzs * plane;
-    const float inv_plane = 1.f / (float)plane, inv_nx = 1.f / (float)nx;
+    const double* s0 = src + ((long long)(B.bz0 + z0) * D.ny + B.by0) * D.nx + B.bx0;
+    int zl = t / plane, y = (t - zl * plane) / nx, x = t - zl * plane - y * nx;
+    const int dz = 256 / plane, r256 = 256 - dz * plane, dy = r256 / nx, dx = r256 - dy * nx;
+    int off = (zl * D.ny + y) * D.nx + x;          // element offset from s0
+    int li = (zl * NR + y) * RS + x;               // LDS index
+    const int doff = (dz * D.ny + dy) * D.nx + dx, dli = (dz * NR + dy) * RS + dx;
+    const int cx_off = D.nx - nx, cx_li = RS - nx;               // x carry
+    const int cy_off = (D.ny - ny) * D.nx, cy_li = (NR - ny) * RS; // y carry
     constexpr int NI = (ZS * NP * NP + 255) / 256;
     double v[NI];
     int at[NI];
     unsigned long long wall = 0;
 #pragma unroll
     for (int i = 0; i < NI; ++i) {
-      const int e = min(t + 256 * i, tot - 1);
-      const int zl = (int)(((float)e + 0.5f) * inv_plane), rem = e - zl * plane;
-      const int y = (int)(((float)rem + 0.5f) * inv_nx), x = rem - y * nx;
-      v[i] = src[((long long)(B.bz0 + z0 + zl) * D.ny + (B.by0 + y)) * D.nx + (B.bx0 + x)];
-      at[i] = (zl * NR + y) * RS + x;
+      v[i] = s0[t + 256 * i < tot ? off : 0];
+      at[i] = li;
       if (box_wall(q, x, y, z0 + zl)) wall |= 1ull << i;
+      x += dx; y += dy; zl += dz; off += doff; li += dli;
+      if (x >= nx) { x -= nx; ++y; off += cx_off; li += cx_li; }
+      if (y >= ny) { y -= ny; ++zl; off += cy_off; li += cy_li; }
     }
 #pragma unroll
     for (int i = 0; i < NI; ++i)
@@ -336,15 +345,22 @@ __global__ __launch_bounds__(256) void k_mpass_c(const __bf16* __restrict__ W, d
   load_tab(ty, tb + (q == 1 ? B.mdctT[1] : B.mdst[1]), l16, g);
   load_tab(tx, tb + (q == 0 ? B.mdctT[0] : B.mdst[0]), l16, g);
 
-  {  // chunk z0 / 4 of the slab's columns (p, q'): X[(p, zl)][q']
-    const int plane = ny * nx;
+  {  // chunk z0 / 4 of the slab's columns (p, q'): X[(p, zl)][q'], two
+     // neighbouring columns (q', q'+1) per step: one 16-byte read of W and
+     // 4-byte LDS stores (column ny, when ny is odd, is masked on reading)
+    const int plane = ny * nx, npair = (ny + 1) >> 1;
     const __bf16* Wc = W + B.w_off + (long long)q * box_wvol(B, true) + (long long)(z0 / 4) * plane * 4;
-    const float inv_ny = 1.f / (float)ny;
-    for (int e = t; e < plane; e += 256) {
-      const int p = (int)(((float)e + 0.5f) * inv_ny), qq = e - p * ny;
-      const bf16x4 v = *reinterpret_cast<const bf16x4*>(Wc + e * 4);
+    const float inv_np = 1.f / (float)npair;
+    for (int e = t; e < nx * npair; e += 256) {
+      const int p = (int)(((float)e + 0.5f) * inv_np), qq = 2 * (e - p * npair);
+      const __bf16* src = Wc + (p * ny + qq) * 4;
+      const bf16x4 v0 = *reinterpret_cast<const bf16x4*>(src);
+      const bf16x4 v1 = qq + 1 < ny ? *reinterpret_cast<const bf16x4*>(src + 4) : zero4();
 #pragma unroll
-      for (int zl = 0; zl < ZS; ++zl) X[(p * ZS + zl) * RS + qq] = v[zl];
+      for (int zl = 0; zl < ZS; ++zl) {
+        typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+        *reinterpret_cast<bf16x2*>(X + (p * ZS + zl) * RS + qq) = bf16x2{v0[zl], v1[zl]};
+      }
     }
   }
   __syncthreads();
@@ -370,6 +386,7 @@ __global__ __launch_bounds__(256) void k_mpass_c(const __bf16* __restrict__ W, d
   const DomainDev& D = doms[B.dom];
   double* dst = z + D.offset + (long long)q * D.nz * D.ny * D.nx;
   const double cq = coarse ? coarse[(long long)q * nsub + B.sub] : 0.0;
+  const long long pz = (long long)D.ny * D.nx;
 #pragma unroll
   for (int j = 0; j < NT; ++j) {
     const int y = (wave + 4 * j) * 4 + g;         // the lane's rows: (y, zl = 0..3)
@@ -378,14 +395,15 @@ __global__ __launch_bounds__(256) void k_mpass_c(const __bf16* __restrict__ W, d
       const int x = nt * 16 + l16;
       const f32x4 acc = tile_frag<KS>(a[j], tx[nt]);
       if (y < ly0 || y >= ly1 || x < lx0 || x >= lx1) continue;
+      const int gy = B.by0 + y, gx = B.bx0 + x;
+      double* col = dst + ((long long)(B.bz0 + z0) * D.ny + gy) * D.nx + gx;   // (z0, y, x)
 #pragma unroll
       for (int zl = 0; zl < ZS; ++zl) {
         const int lz = z0 + zl;
         if (zl >= nzs || lz < lz0 || lz >= lz1) continue;
-        const int gz = B.bz0 + lz, gy = B.by0 + y, gx = B.bx0 + x;
         double val = (double)acc[zl];
-        if (coarse && !box_wall(q, gx, gy, gz)) val += cq;
-        dst[((long long)gz * D.ny + gy) * D.nx + gx] = val;
+        if (coarse && !box_wall(q, gx, gy, B.bz0 + lz)) val += cq;
+        col[(long long)zl * pz] = val;
       }
     }
   }
