@@ -215,9 +215,6 @@ __device__ __forceinline__ bool box_wall(int q, int x, int y, int z) {
   return q == 0 ? (y == 0 || z == 0) : (q == 1 ? (x == 0 || z == 0) : (x == 0 || y == 0));
 }
 
-// e / d for 0 <= e < 2^24 from a precomputed 1/d: the rounding error of
-// (e + 1/2) / d in FP64 is far below the 1/(2d) margin to the next integer.
-__device__ __forceinline__ int qdiv(int e, double inv_d) { return (int)(((double)e + 0.5) * inv_d); }
 
 // Passes A and C run 128-thread workgroups over slabs of 128/NP planes: the
 // FP64 slab then needs ~28 KB of LDS (5 workgroups per CU instead of 2 with
@@ -254,18 +251,26 @@ __global__ __launch_bounds__(kAC) void k_pass_a(const double* __restrict__ r, T*
   const int plane = ny * nx;
   const int tot = nzs * plane;
   const int t = threadIdx.x;
-  const double inv_plane = 1.0 / plane, inv_nx = 1.0 / nx;
 
   static_assert(MAXE <= 64, "wall flags are kept in one 64-bit mask");
-  double vals[MAXE];                              // S^gamma: gather the slab
+  // S^gamma: gather the slab.  A thread's elements t + kAC i are stepped from
+  // its first one by the fixed increment of kAC elements (two carries), with
+  // no per-element division; loads of out-of-slab steps read element 0.
+  const double* s0 = src + ((long long)(B.bz0 + z0) * D.ny + B.by0) * D.nx + B.bx0;
+  int zl = t / plane, y = (t - zl * plane) / nx, x = t - zl * plane - y * nx;
+  const int dz = kAC / plane, rk = kAC - dz * plane, dy = rk / nx, dx = rk - dy * nx;
+  int off = (zl * D.ny + y) * D.nx + x;
+  const int doff = (dz * D.ny + dy) * D.nx + dx;
+  const int cx_off = D.nx - nx, cy_off = (D.ny - ny) * D.nx;
+  double vals[MAXE];
   unsigned long long wall = 0;
 #pragma unroll
   for (int i = 0; i < MAXE; ++i) {
-    const int e = min(t + kAC * i, tot - 1);
-    const int zl = qdiv(e, inv_plane), rem = e - zl * plane;
-    const int y = qdiv(rem, inv_nx), x = rem - y * nx;
+    vals[i] = s0[t + kAC * i < tot ? off : 0];
     if (box_wall(q, x, y, z0 + zl)) wall |= 1ull << i;
-    vals[i] = src[((B.bz0 + z0 + zl) * D.ny + (B.by0 + y)) * D.nx + (B.bx0 + x)];
+    x += dx; y += dy; zl += dz; off += doff;
+    if (x >= nx) { x -= nx; ++y; off += cx_off; }
+    if (y >= ny) { y -= ny; ++zl; off += cy_off; }
   }
 #pragma unroll
   for (int i = 0; i < MAXE; ++i) {
@@ -448,17 +453,24 @@ __global__ __launch_bounds__(kAC) void k_pass_c(const T* __restrict__ W, double*
   const DomainDev& D = doms[B.dom];
   double* dst = z + D.offset + (long long)q * D.nz * D.ny * D.nx;
   const double cq = coarse ? coarse[(long long)q * nsub + B.sub] : 0.0;
-  const double inv_op = 1.0 / oplane, inv_sx = 1.0 / B.sx;
+  // owned element t + kAC i: (zl, y, x) stepped by the fixed increment of kAC
+  // (two carries) with its slab index and its place in z
+  const int sx = B.sx, sy = B.sy;
+  int zl = t / oplane, y = (t - zl * oplane) / sx, x = t - zl * oplane - y * sx;
+  const int dz = kAC / oplane, rk = kAC - dz * oplane, dy = rk / sx, dx = rk - dy * sx;
+  int bi = (lz0 + zl - z0) * plane + (ly0 + y) * nx + lx0 + x;
+  long long go = ((long long)(B.bz0 + lz0 + zl) * D.ny + (B.by0 + ly0 + y)) * D.nx + B.bx0 + lx0 + x;
+  const int dbi = dz * plane + dy * nx + dx;
+  const long long dgo = ((long long)dz * D.ny + dy) * D.nx + dx;
+  const int cx_bi = nx - sx, cy_bi = plane - sy * nx;
+  const long long cx_go = D.nx - sx, cy_go = (long long)(D.ny - sy) * D.nx;
   for (int e = t; e < otot; e += kAC) {
-    const int zl = qdiv(e, inv_op);
-    const int rem = e - zl * oplane;
-    const int y = qdiv(rem, inv_sx);
-    const int x = rem - y * B.sx;
-    const int lz = lz0 + zl, ly = ly0 + y, lx = lx0 + x;
-    const int gz = B.bz0 + lz, gy = B.by0 + ly, gx = B.bx0 + lx;
-    double val = (double)buf[(lz - z0) * plane + ly * nx + lx];
-    if (coarse && !box_wall(q, gx, gy, gz)) val += cq;
-    dst[(gz * D.ny + gy) * D.nx + gx] = val;
+    double val = (double)buf[bi];
+    if (coarse && !box_wall(q, B.bx0 + lx0 + x, B.by0 + ly0 + y, B.bz0 + lz0 + zl)) val += cq;
+    dst[go] = val;
+    x += dx; y += dy; zl += dz; bi += dbi; go += dgo;
+    if (x >= sx) { x -= sx; ++y; bi += cx_bi; go += cx_go; }
+    if (y >= sy) { y -= sy; ++zl; bi += cy_bi; go += cy_go; }
   }
 }
 
