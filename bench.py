@@ -537,8 +537,9 @@ def main():
     ap.add_argument("--ref-in", default=None, help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: the solver has no multi-GPU path "
-              "(see DESIGN.md for how it would shard)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the solver has no multi-GPU path; "
+              "its kernels run one GPU's share of a sharded grid at its real shape",
+              file=sys.stderr)
         sys.exit(2)
     if args.leg:
         run_leg(args)
