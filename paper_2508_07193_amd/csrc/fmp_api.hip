@@ -28,7 +28,7 @@ using namespace fmp;
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr int kTB = 64;         // row stride of the bf16 tables
+constexpr int kTB = 96;         // row stride of the bf16 tables (largest class)
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 constexpr int kScal = 256;      // doubles in the scalar area
@@ -356,8 +356,11 @@ fmp_status fmp_setup_subdomains(const fmp_domain_desc* domains, int32_t n_domain
           B.vol = (long long)B.nx * B.ny * B.nz;
           B.wzp = (B.nz + 3) / 4 * 4;
           if (std::min(B.nx, std::min(B.ny, B.nz)) < 2) return FMP_ERR_INVALID_ARG;
-          if (std::max(B.nx, std::max(B.ny, B.nz)) > kMaxSide) h->precond_ok = false;
-          else sides_used[B.nx] = sides_used[B.ny] = sides_used[B.nz] = 1;
+          const int side_max = std::max(B.nx, std::max(B.ny, B.nz));
+          if (side_max > kMaxSide || (side_max > kMaxSideVec && h->prec != FMP_BF16))
+            h->precond_ok = false;
+          else
+            sides_used[B.nx] = sides_used[B.ny] = sides_used[B.nz] = 1;
           // alpha = c / mean eps over the owned cells
           double alpha = D.c;
           if (D.eps_block) {
@@ -435,7 +438,7 @@ fmp_status fmp_setup_subdomains(const fmp_domain_desc* domains, int32_t n_domain
         for (int j = 0; j < kTS; ++j) base[kTS * kTS + i * kTS + j] = c[j * kTS + i];
       std::copy(s.begin(), s.end(), base + 2 * kTS * kTS);
       std::copy(g.begin(), g.end(), base + 3 * kTS * kTS);
-      for (int tau = 0; tau < 2; ++tau) {
+      for (int tau = 0; tau < 2 && n <= kMaxSideVec; ++tau) {   // vector-ALU sides only
         const std::vector<double>& T = tau == 0 ? c : s;   // full n x n matrix, stride kTS
         double* hb = base + 3 * kTS * kTS + kTS + tau * 4 * kHS * kHS;
         const int P = (n - tau) / 2, mid = (n - tau) & 1, cm = (n - 1 + tau) / 2;
@@ -655,7 +658,7 @@ fmp_status fmp_apply_precond(fmp_handle h, const double* r, double* z, void* str
   if (!h || !r || !z) return FMP_ERR_INVALID_ARG;
   if (overlaps(r, z, h->len * 8)) return FMP_ERR_ALIAS;
   if (!h->precond_ok) {
-    h->err = "a box side exceeds the largest compiled transform size (48)";
+    h->err = "a box side exceeds the largest compiled transform size (48 cells with FP64 or FP32 transforms, 96 with BF16)";
     return FMP_ERR_UNSUPPORTED;
   }
   hipStream_t s = (hipStream_t)stream;

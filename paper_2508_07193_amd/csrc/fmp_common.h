@@ -12,15 +12,18 @@
 
 namespace fmp {
 
-// Largest box side with a compiled transform class, and the row stride of
-// every transform table (tables are stored kTS x kTS, zero padded).
-constexpr int kMaxSide = 48;
-constexpr int kTS = 48;
-constexpr int kHS = 24;   // stride of the half (butterfly) tables
+// Largest box side with a compiled transform class (the matrix-core passes),
+// the largest side of the vector-ALU passes (FP64 / FP32), and the row stride
+// of every full transform table (stored kTS x kTS, zero padded).
+constexpr int kMaxSide = 96;
+constexpr int kMaxSideVec = 48;
+constexpr int kTS = 96;
+constexpr int kHS = 24;   // stride of the half (butterfly) tables, sides <= kMaxSideVec
 
 // Transform size classes: a box of largest side n runs the kernels compiled
 // for the smallest class >= n (zero-padded rows/columns cost flops only).
-constexpr int kClasses[] = {8, 16, 24, 26, 32, 34, 40, 48};
+// Classes above kMaxSideVec exist on the matrix-core (BF16) path only.
+constexpr int kClasses[] = {8, 16, 24, 26, 32, 34, 40, 48, 64, 96};
 constexpr int kNumClasses = sizeof(kClasses) / sizeof(kClasses[0]);
 
 struct DomainDev {

@@ -35,7 +35,7 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
-constexpr int kTB = 64;   // bf16 table row stride
+constexpr int kTB = 96;   // bf16 table row stride (largest class)
 constexpr int ZS = 4;     // z planes per pass A / C work item
 
 template <int NP>
@@ -166,22 +166,28 @@ __global__ __launch_bounds__(256) void k_mpass_a(const double* __restrict__ r, _
     const int doff = (dz * D.ny + dy) * D.nx + dx, dli = (dz * NR + dy) * RS + dx;
     const int cx_off = D.nx - nx, cx_li = RS - nx;               // x carry
     const int cy_off = (D.ny - ny) * D.nx, cy_li = (NR - ny) * RS; // y carry
+    // elements in flight per thread: all of them up to 40, else chunks of 16
     constexpr int NI = (ZS * NP * NP + 255) / 256;
-    double v[NI];
-    int at[NI];
-    unsigned long long wall = 0;
+    constexpr int CH = NI <= 40 ? NI : 16;
+    constexpr int NCH = (NI + CH - 1) / CH;
+#pragma unroll 1
+    for (int ch = 0; ch < NCH; ++ch) {
+      double v[CH];
+      int at[CH];
+      unsigned long long wall = 0;
 #pragma unroll
-    for (int i = 0; i < NI; ++i) {
-      v[i] = s0[t + 256 * i < tot ? off : 0];
-      at[i] = li;
-      if (box_wall(q, x, y, z0 + zl)) wall |= 1ull << i;
-      x += dx; y += dy; zl += dz; off += doff; li += dli;
-      if (x >= nx) { x -= nx; ++y; off += cx_off; li += cx_li; }
-      if (y >= ny) { y -= ny; ++zl; off += cy_off; li += cy_li; }
+      for (int i = 0; i < CH; ++i) {
+        v[i] = s0[t + 256 * (ch * CH + i) < tot ? off : 0];
+        at[i] = li;
+        if (box_wall(q, x, y, z0 + zl)) wall |= 1ull << i;
+        x += dx; y += dy; zl += dz; off += doff; li += dli;
+        if (x >= nx) { x -= nx; ++y; off += cx_off; li += cx_li; }
+        if (y >= ny) { y -= ny; ++zl; off += cy_off; li += cy_li; }
+      }
+#pragma unroll
+      for (int i = 0; i < CH; ++i)
+        if (t + 256 * (ch * CH + i) < tot) S[at[i]] = (__bf16)(((wall >> i) & 1ull) ? 0.0 : v[i]);
     }
-#pragma unroll
-    for (int i = 0; i < NI; ++i)
-      if (t + 256 * i < tot) S[at[i]] = (__bf16)(((wall >> i) & 1ull) ? 0.0 : v[i]);
   }
   __syncthreads();
 
@@ -189,7 +195,8 @@ __global__ __launch_bounds__(256) void k_mpass_a(const double* __restrict__ r, _
   load_rows<NT, KS, RS>(a, S, wave, l16, g, nx,
                         [&](int row) { return row % NR < ny && row / NR < nzs; });
   __syncthreads();                                // S is overwritten by Y from here
-  load_tab(ty, tb + (q == 1 ? B.mdct[1] : B.mdst[1]), l16, g);
+  constexpr bool kLarge = NP > 48;                // large classes hold one table at a time
+  if (!kLarge) load_tab(ty, tb + (q == 1 ? B.mdct[1] : B.mdst[1]), l16, g);
 #pragma unroll
   for (int j = 0; j < NT; ++j) {
     const int row = (wave + 4 * j) * 16 + 4 * g, zl = row / NR, y = row - zl * NR;
@@ -202,6 +209,7 @@ __global__ __launch_bounds__(256) void k_mpass_a(const double* __restrict__ r, _
   __syncthreads();
 
   // y: D[(p, zl)][q'] = sum_y Y[(p, zl)][y] T[q'][y]  ->  chunk z0 / 4 of column (p, q')
+  if (kLarge) load_tab(ty, tb + (q == 1 ? B.mdct[1] : B.mdst[1]), l16, g);
   load_rows<NT, KS, RS>(a, S, wave, l16, g, ny, [](int) { return true; });
   __bf16* Wc = W + B.w_off + (long long)q * box_wvol(B, true) + (long long)(z0 / 4) * ny * nx * 4;
 #pragma unroll
@@ -342,8 +350,9 @@ __global__ __launch_bounds__(256) void k_mpass_c(const __bf16* __restrict__ W, d
   const int lx0 = B.ox0 - B.bx0, lx1 = lx0 + B.sx;
   if (z0 + ZS <= lz0 || z0 >= lz1) return;         // no owned plane in this slab
   bf16x8 ty[NT][KS], tx[NT][KS], a[NT][KS];
+  constexpr bool kLarge = NP > 48;                // large classes hold one table at a time
   load_tab(ty, tb + (q == 1 ? B.mdctT[1] : B.mdst[1]), l16, g);
-  load_tab(tx, tb + (q == 0 ? B.mdctT[0] : B.mdst[0]), l16, g);
+  if (!kLarge) load_tab(tx, tb + (q == 0 ? B.mdctT[0] : B.mdst[0]), l16, g);
 
   {  // chunk z0 / 4 of the slab's columns (p, q'): X[(p, zl)][q'], two
      // neighbouring columns (q', q'+1) per step: one 16-byte read of W and
@@ -382,6 +391,7 @@ __global__ __launch_bounds__(256) void k_mpass_c(const __bf16* __restrict__ W, d
   __syncthreads();
 
   // inverse x: D[(y, zl)][l] = sum_p U[(y, zl)][p] Ti[l][p], then S^0T
+  if (kLarge) load_tab(tx, tb + (q == 0 ? B.mdctT[0] : B.mdst[0]), l16, g);
   load_rows<NT, KS, RS>(a, X, wave, l16, g, nx, [](int) { return true; });
   const DomainDev& D = doms[B.dom];
   double* dst = z + D.offset + (long long)q * D.nz * D.ny * D.nx;
@@ -419,6 +429,8 @@ __global__ __launch_bounds__(256) void k_mpass_c(const __bf16* __restrict__ W, d
     case 5: CALL(34); break;                            \
     case 6: CALL(40); break;                            \
     case 7: CALL(48); break;                            \
+    case 8: CALL(64); break;                            \
+    case 9: CALL(96); break;                            \
     default: return hipErrorInvalidValue;               \
   }
 
