@@ -32,11 +32,11 @@ HBM_PEAK_GBS = 8000.0
 # since, traffic is null.
 TRAFFIC = {
     "k_mupdate": (1.0000, {"fmp_krylov.hip": "007a4daff79be785b7e7b45be9ae1a9a36d275d3d7dce1a34dbc36c12cb8fce5",
-                          "fmp_common.h": "4b12919ac40ea6352d4233abf1f834b5a53a20f2fd05c1e70c910735a7dc8db7"}),
+                          "fmp_common.h": "33d0696ad75f124f9c64fd5b11a0246e476868a01db6b9078db1495178bab090"}),
     "k_mdot": (1.0000, {"fmp_krylov.hip": "007a4daff79be785b7e7b45be9ae1a9a36d275d3d7dce1a34dbc36c12cb8fce5",
-                          "fmp_common.h": "4b12919ac40ea6352d4233abf1f834b5a53a20f2fd05c1e70c910735a7dc8db7"}),
+                          "fmp_common.h": "33d0696ad75f124f9c64fd5b11a0246e476868a01db6b9078db1495178bab090"}),
     "k_curlcurl": (1.0363, {"fmp_stencil.hip": "7fd7ff0c4eba81bdabfa8cbe6fb11d031c2ed4066c6f3f3a160de218c3ec3b12",
-                          "fmp_common.h": "4b12919ac40ea6352d4233abf1f834b5a53a20f2fd05c1e70c910735a7dc8db7"}),
+                          "fmp_common.h": "33d0696ad75f124f9c64fd5b11a0246e476868a01db6b9078db1495178bab090"}),
 }
 
 
