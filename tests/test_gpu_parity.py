@@ -444,3 +444,22 @@ def test_autotune_keeps_results_bitwise():
     h = api.Handle(doms[:1], device=DEV)
     with pytest.raises(api.FlashMPError, match="UNSUPPORTED"):
         h.autotune(r[:h.length].contiguous())
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("precision,u", [("fp32", 2.0**-24), ("bf16", 2.0**-8)])
+def test_full_256_sampled_reduced_precision(precision, u):
+    """256^3 C3 workload with FP32 / BF16 transforms: sampled subdomain blocks
+    (corner, edge, face, interior) within the 12u bound of the smaller cases."""
+    P = inputs.make_problem("c3")
+    eps_cell = eps_cell_of(P)
+    h = handle_for(P, precision=precision)
+    z = h.new_vector()
+    h.apply_precond(dev(P["rhs"]), z)
+    zo = host(z, P["rhs"].shape)
+    which = [0, 7, 63, 511, 4 * 64 + 3 * 8 + 4]
+    blocks = ras.ras_apply_subset(P["rhs"], P["c"], P["sub"], 1, eps_cell, which)
+    for idx, (own, blk) in blocks.items():
+        (x0, x1), (y0, y1), (z0, z1) = own
+        err = rel2(zo[:, z0:z1, y0:y1, x0:x1], blk)
+        assert err < 12 * u, (idx, err)
