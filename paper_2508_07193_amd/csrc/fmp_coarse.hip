@@ -120,14 +120,19 @@ __global__ __launch_bounds__(kT) void k_gemv(const __hip_bfloat16* __restrict__ 
 
 // ---------------------------------------------------------------- judge
 // d(q, k, j, i): the piecewise-constant correction on unknown slots
+// v / d for 0 <= v < 2^20 from a precomputed float 1/d: the rounding error of
+// (v + 1/2) / d in FP32 stays far below its 1/(2d) margin to the next integer
+__device__ __forceinline__ int fquot(int v, float inv_d) { return (int)(((float)v + 0.5f) * inv_d); }
+
 struct CoarseField {
   const double* yc;
   int nsub;
   DomainDev D;
+  float inv_sx, inv_sy, inv_sz;
   __device__ __forceinline__ double operator()(int q, int k, int j, int i) const {
     if (i < 0 || j < 0 || k < 0 || i >= D.nx || j >= D.ny || k >= D.nz) return 0.0;
     if (is_wall(q, i, j, k)) return 0.0;
-    const int s = D.sub0 + ((k / D.sz) * D.py + j / D.sy) * D.px + i / D.sx;
+    const int s = D.sub0 + (fquot(k, inv_sz) * D.py + fquot(j, inv_sy)) * D.px + fquot(i, inv_sx);
     return yc[(long long)q * nsub + s];
   }
 };
@@ -145,7 +150,8 @@ __device__ double apply_A_at(const F& d, const DomainDev& D, const double* __res
   if (is_wall(q, i, j, k)) return 0.0;
   const double c0 = d(q, k, j, i);
   // interior of a subdomain, away from walls: K d = 0
-  const int li = i % D.sx, lj = j % D.sy, lk = k % D.sz;
+  const int li = i - fquot(i, d.inv_sx) * D.sx, lj = j - fquot(j, d.inv_sy) * D.sy;
+  const int lk = k - fquot(k, d.inv_sz) * D.sz;
   if (li >= 1 && li + 1 < D.sx && lj >= 1 && lj + 1 < D.sy && lk >= 1 && lk + 1 < D.sz &&
       i >= 2 && j >= 2 && k >= 2 && i + 2 < D.nx && j + 2 < D.ny && k + 2 < D.nz)
     return c0;
@@ -185,18 +191,38 @@ __global__ __launch_bounds__(kT) void k_judge(const double* __restrict__ v,
   __shared__ double red[4][2];
   double a0 = 0.0, a1 = 0.0;
   const long long stride = (long long)kRedBlocks * kT;
-  int d = 0;
+  // the element -> (q, k, j, i) decomposition uses quotients from reciprocals
+  // computed once per domain (exact: FP64 for offsets within a vector and a
+  // plane, FP32 for single coordinates, which stay below 2^20)
+  int d = -1;
+  DomainDev D{};
+  long long cs = 1;
+  int pl = 1;
+  double inv_cs = 1.0, inv_pl = 1.0;
+  double inv_nx = 1.0;
+  float inv_sx = 1.f, inv_sy = 1.f, inv_sz = 1.f;
   for (long long e = (long long)blockIdx.x * kT + threadIdx.x; e < len; e += stride) {
-    while (d + 1 < ndom && e >= doms[d + 1].offset) ++d;
-    const DomainDev D = doms[d];
+    int dn = d < 0 ? 0 : d;
+    while (dn + 1 < ndom && e >= doms[dn + 1].offset) ++dn;
+    if (dn != d) {
+      d = dn;
+      D = doms[d];
+      pl = D.ny * D.nx;
+      cs = (long long)D.nz * pl;
+      inv_cs = 1.0 / (double)cs;
+      inv_pl = 1.0 / (double)pl;
+      inv_nx = 1.0 / (double)D.nx;
+      inv_sx = 1.f / (float)D.sx;
+      inv_sy = 1.f / (float)D.sy;
+      inv_sz = 1.f / (float)D.sz;
+    }
     const long long loc = e - D.offset;
-    const long long cs = (long long)D.nz * D.ny * D.nx;
-    const int q = (int)(loc / cs);
+    const int q = (int)(((double)loc + 0.5) * inv_cs);
     const long long rem = loc - q * cs;
-    const int k = (int)(rem / ((long long)D.ny * D.nx));
-    const int rr = (int)(rem - (long long)k * D.ny * D.nx);
-    const int j = rr / D.nx, i = rr - j * D.nx;
-    const CoarseField F{yc, nsub, D};
+    const int k = (int)(((double)rem + 0.5) * inv_pl);
+    const int rr = (int)(rem - (long long)k * pl);
+    const int j = (int)(((double)rr + 0.5) * inv_nx), i = rr - j * D.nx;
+    const CoarseField F{yc, nsub, D, inv_sx, inv_sy, inv_sz};
     const double ad = apply_A_at(F, D, eps, q, k, j, i);
     const double rl = v[e] - w[e];
     const double rp = rl + ad;
