@@ -40,6 +40,29 @@ TRAFFIC = {
 }
 
 
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+
+def transform_flops_per_apply(n, sub, overlap=1):
+    """FP64 flops of one preconditioner apply's transforms on an n^3 grid cut
+    into sub^3 subdomains (boxes = owned block + overlap, clipped at walls):
+    per box, component and axis, every pencil along that axis is contracted
+    forward and back with the even/odd butterfly, n_axis^2 / 2 FMAs each way."""
+    def sides(nn, s):
+        out = []
+        for a in range(0, nn, s):
+            out.append(min(nn, a + s + overlap) - max(0, a - overlap))
+        return out
+    sx = sides(n, sub[0]); sy = sides(n, sub[1]); sz = sides(n, sub[2])
+    fma = 0
+    for bz in sz:
+        for by in sy:
+            for bx in sx:
+                for (na, other) in ((bx, by * bz), (by, bx * bz), (bz, bx * by)):
+                    fma += 3 * other * (na * na / 2.0) * 2      # 3 components, forward + inverse
+    return 2.0 * fma
+
+
 def traffic_ratio(name):
     import hashlib
     if name not in TRAFFIC:
@@ -474,6 +497,16 @@ def main_leg(args):
         "precond_apply": roof("precond_apply", "precond apply (passes A, B, C)", 16.0 * n_unk, t_pre,
                               "16 B per unknown (r in, z out); staging traffic excluded"),
     }
+    P = C["P"]
+    tf = transform_flops_per_apply(P["nx"], P["sub"])
+    tach = tf / (t_pre * 1e-3) / 1e12
+    roofs["precond_apply_fp64_alu"] = dict(
+        bound="alu", achieved=round(tach, 2), peak=FP64_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
+        frac=round(tach / FP64_VECTOR_PEAK_TFLOPS, 3), traffic=None,
+        kernel="precond apply (passes A, B, C), FP64 transform arithmetic",
+        flops_per_launch=round(tf), avg_ms=round(t_pre, 4),
+        algorithmic_flops="per box, component and axis: pencils x n_axis^2/2 FMAs, forward and "
+                          "inverse (even/odd butterfly), 2 flops per FMA")
     share = {"k_mupdate": pinfo["t_orth_update_ms"], "k_mdot": pinfo["t_orth_dot_ms"],
              "precond_apply": pinfo["t_precond_ms"], "k_curlcurl": pinfo["t_spmv_ms"]}
     dominant = max(share, key=share.get)
