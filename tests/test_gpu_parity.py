@@ -463,3 +463,32 @@ def test_full_256_sampled_reduced_precision(precision, u):
         (x0, x1), (y0, y1), (z0, z1) = own
         err = rel2(zo[:, z0:z1, y0:y1, x0:x1], blk)
         assert err < 12 * u, (idx, err)
+
+
+@pytest.mark.parametrize("precision,tol,iters", [("fp64", 1e-13, 1), ("fp32", 1e-5, 2),
+                                                  ("bf16", 5e-2, 5)])
+def test_degenerate_c_zero_is_identity(precision, tol, iters):
+    """c = 0: A = I and every box solve is a forward then an inverse orthonormal
+    transform, so M^-1 r = r on the unknowns up to the transform's rounding and
+    BiCGSTAB stops within a step or two; a Crank-Nicolson step with
+    dt = 2 sqrt(c) = 0 starts from a zero residual and leaves E and the H
+    unknowns unchanged, with zeros written on the H wall slots."""
+    n, sub = 24, 8
+    r = inputs.normal_rhs(np.random.default_rng(21), n, n, n)
+    h = api.Handle([dict(nx=n, ny=n, nz=n, c=0.0, sub=(sub, sub, sub))], precision=precision,
+                   device=DEV)
+    z = h.new_vector()
+    h.apply_precond(dev(r), z)
+    assert np.abs(host(z, r.shape) - r).max() <= tol * np.abs(r).max()
+    x = h.new_vector()
+    info = h.solve(dev(r), x, solver="bicgstab", rtol=1e-8, max_iter=20)
+    assert info["status"] == "FMP_OK" and info["iterations"] <= iters, info
+    if precision == "fp64":
+        E, H = dev(r), dev(r[::-1].copy() * 0.5)
+        E0, H0 = E.clone(), H.clone()
+        h.cn_step(E, H, solver="bicgstab", rtol=1e-12, max_iter=20)
+        torch.cuda.synchronize()
+        assert torch.equal(E, E0)
+        from oracle import fdtd
+        mask = torch.from_numpy(fdtd.h_mask(n, n, n).ravel()).to(DEV)
+        assert torch.equal(H[mask], H0[mask]) and float(H[~mask].abs().max()) == 0.0
