@@ -295,11 +295,11 @@ __global__ __launch_bounds__(kAC) void k_pass_a(const double* __restrict__ r, T*
 }
 
 // ---------------------------------------------------------------- pass B
-// FP64 pass B holds a 34-long column per lane; computing two contraction rows
-// at a time there costs an occupancy step (3 -> 2 waves per SIMD), so it
-// takes one row at a time; FP32 has the registers to spare.
-template <typename T>
-constexpr bool kPassBTwo = sizeof(T) == 4;
+// Two forms.  The register-resident one (FP32) stages the whole spectral
+// column set of a workgroup in LDS between the forward transform, the solve
+// and the inverse, and computes two contraction rows at a time.  The ring
+// form (FP64, further below) exchanges one wavenumber at a time: the FP64
+// column set would need 52 KB of LDS per workgroup and cap occupancy there.
 
 // The column is held in registers when its length nz is a compile-time
 // constant (nz = NP or NP - 1, which covers every box of a class at the
@@ -309,13 +309,13 @@ constexpr bool kPassBTwo = sizeof(T) == 4;
 template <typename T, int NP, int NZ, int TZ>
 __device__ __forceinline__ void colz_fwd(const T* __restrict__ tabz, const T (&v)[NP],
                                          T (*exq)[64], int lane) {
-  fwd_bfly<T, NP / 2, kPassBTwo<T>>(tabz, half_geom(NZ, TZ), [&](int l) { return v[l]; },
+  fwd_bfly<T, NP / 2, true>(tabz, half_geom(NZ, TZ), [&](int l) { return v[l]; },
                                      [&](int r, T val) { exq[r][lane] = val; });
 }
 template <typename T, int NP, int NZ, int TZ>
 __device__ __forceinline__ void colz_inv(const T* __restrict__ tabz, const T (&e)[NP], T* col,
                                          int plane, bool active) {
-  inv_bfly<T, NP / 2, kPassBTwo<T>>(tabz, half_geom(NZ, TZ), [&](int r) { return e[r]; },
+  inv_bfly<T, NP / 2, true>(tabz, half_geom(NZ, TZ), [&](int r) { return e[r]; },
                                      [&](int l, T val) {
                                        if (active) col[(long long)l * plane] = val;
                                      });
@@ -356,7 +356,7 @@ __global__ __launch_bounds__(192) void k_pass_b(T* __restrict__ W, const BoxDev*
 #pragma unroll
     for (int l = 0; l < NP; ++l) ex[q][l][lane] = v[l];
     const Half gz = half_geom(nz, tz);
-    fwd_bfly<T, NH, kPassBTwo<T>>(tabz, gz, [&](int l) { return ex[q][l][lane]; },
+    fwd_bfly<T, NH, true>(tabz, gz, [&](int l) { return ex[q][l][lane]; },
                                   [&](int r, T val) { ex[q][r][lane] = val; });
   }
   __syncthreads();
@@ -393,10 +393,149 @@ __global__ __launch_bounds__(192) void k_pass_b(T* __restrict__ W, const BoxDev*
     if (tz == 0) colz_inv<T, NP, NP - 1, 0>(tabz, v, col, plane, active);
     else colz_inv<T, NP, NP - 1, 1>(tabz, v, col, plane, active);
   } else {
-    inv_bfly<T, NH, kPassBTwo<T>>(tabz, half_geom(nz, tz), [&](int r) { return ex[q][r][lane]; },
+    inv_bfly<T, NH, true>(tabz, half_geom(nz, tz), [&](int r) { return ex[q][r][lane]; },
                                   [&](int l, T val) {
                                     if (active) col[(long long)l * plane] = val;
                                   });
+  }
+}
+
+// Pass B, ring form.  The three waves (one per component) walk the z
+// wavenumbers together, the even ones first, then the odd ones.  At each
+// wavenumber a wave forms its component's forward coefficient (one half-table
+// row times the butterfly sums or differences), the three coefficients meet
+// in a two-slot LDS ring, every wave solves eq. (12) for its own component,
+// and it adds the solved coefficient times the same table row into the
+// inverse's even or odd accumulators (the inverse half tables are the
+// transposes of the forward ones).  A table row is read once for both
+// directions, and the LDS holds 2 x 3 x 64 values instead of the whole
+// spectral column set.  Within one sweep a wave uses one butterfly half and
+// one accumulator only: DCT-II takes its even modes from the sums and its odd
+// modes from the differences, DST-I the reverse, so the first sweep runs
+// over (sums, even accumulators) for E_z and (differences, odd accumulators)
+// for E_x, E_y, and the second sweep over the other pair.  Three of the four
+// half-length arrays are live at a time.
+// FP64 only: with FP32 the register-resident form above is faster (135 us
+// against 154 us or more for ring forms on the 512 boxes of 34^3 at 256^3),
+// as its occupancy is not LDS-bound there.
+template <typename T>
+constexpr bool kPassBRing = sizeof(T) == 8;
+
+template <typename T, int NP>
+__global__ __launch_bounds__(192) void k_pass_b_ring(T* __restrict__ W,
+                                                     const BoxDev* __restrict__ boxes,
+                                                     const int4* __restrict__ work,
+                                                     const T* __restrict__ tab) {
+  constexpr int NH = NP / 2;
+  static_assert(NP % 2 == 0, "size classes are even");
+  __shared__ T ring[2][3][64];
+  const int4 wk = work[xcd_remap(blockIdx.x, gridDim.x)];
+  const BoxDev& B = boxes[wk.x];
+  const int q = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63;
+  const int nx = B.nx, ny = B.ny, nz = B.nz;
+  const int plane = ny * nx;
+  const int c = wk.y + lane;
+  const bool active = c < plane;
+  T* col = W + B.w_off + (long long)q * B.vol + (active ? c : 0);
+  const int tz = q == 2 ? 0 : 1;                  // DCT-II along z for E_z, DST-I otherwise
+  const T* __restrict__ TS = tab + B.half[2][tz];
+  const T* __restrict__ TD = TS + kHS * kHS;
+  const Half g = half_geom(nz, tz);
+  const int NS = g.P + g.mid;
+
+  // butterfly inputs: pair j is (base + j, n - 1 - j); every load is issued
+  // (at a clamped, in-column index) before any is used.  u1 is the half the
+  // first sweep uses (sums for DCT-II, differences for DST-I), u2 the other.
+  T u1[NH], u2[NH];
+#pragma unroll
+  for (int j = 0; j < NH; ++j) {
+    u1[j] = col[(long long)min(g.base + j, nz - 1) * plane];
+    u2[j] = col[(long long)max(g.n - 1 - j, 0) * plane];
+  }
+#pragma unroll
+  for (int j = 0; j < NH; ++j) {
+    const T xa = u1[j], xb = u2[j];
+    const T sum = j < g.P ? xa + xb : ((j == g.P && g.mid) ? xa : T(0));
+    const T dif = j < g.P ? xa - xb : T(0);
+    u1[j] = tz == 0 ? sum : dif;
+    u2[j] = tz == 0 ? dif : sum;
+  }
+  const T* __restrict__ T1 = tz == 0 ? TS : TD;   // first sweep's half table
+  const T* __restrict__ T2 = tz == 0 ? TD : TS;
+  const int n1 = tz == 0 ? NS : g.P;              // rows of each
+  const int n2 = tz == 0 ? g.P : NS;
+
+  const int yy = active ? c / nx : 0;
+  const int xx = active ? c - yy * nx : 0;
+  const T sx = tab[B.sig[0] + xx];
+  const T sy = tab[B.sig[1] + yy];
+  const T* __restrict__ sz = tab + B.sig[2];
+  const T alpha = (T)B.alpha;
+  const T sxy2 = fmaT<T>(sx, sx, sy * sy);
+
+  // the own component's solve at wavenumber rr from the three coefficients
+  // in ring slot sl
+  auto solve = [&](int rr, int sl) {
+    const T a = ring[sl][0][lane], b = ring[sl][1][lane], d = ring[sl][2][lane];
+    const T s3 = sz[rr];
+    const T dot = fmaT<T>(sx, a, fmaT<T>(sy, b, s3 * d));
+    const T inv = recip<T>(fmaT<T>(alpha, fmaT<T>(s3, s3, sxy2), T(1)));
+    const T own = q == 0 ? a : (q == 1 ? b : d);
+    const T sown = q == 0 ? sx : (q == 1 ? sy : s3);
+    return fmaT<T>(alpha * sown, dot, own) * inv;
+  };
+
+  T acc1[NH], acc2[NH];
+#pragma unroll
+  for (int j = 0; j < NH; ++j) acc1[j] = T(0);
+  // step t = 0 .. NP-1 uses ring slot t & 1: even wavenumbers 2m first
+  // (DCT-II row m of TS, DST-I row m - 1 of TD), then odd ones 2m + 1
+  // (DCT-II row m of TD, DST-I row m of TS)
+#pragma unroll 1
+  for (int m = 0; m < NH; ++m) {
+    const int k = m - tz;
+    const bool has = k >= 0 && k < n1;
+    const T* __restrict__ row = T1 + (has ? k : 0) * kHS;
+    const T f = has ? row_dot<T, NH>(row, u1) : T(0);
+    ring[m & 1][q][lane] = f;
+    __syncthreads();
+    const T e = solve(2 * m, m & 1);
+    if (has) {
+#pragma unroll
+      for (int j = 0; j < NH; ++j) acc1[j] = fmaT<T>(row[j], e, acc1[j]);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < NH; ++j) acc2[j] = T(0);
+#pragma unroll 1
+  for (int m = 0; m < NH; ++m) {
+    const int t = NH + m;
+    const bool has = m < n2;
+    const T* __restrict__ row = T2 + (has ? m : 0) * kHS;
+    const T f = has ? row_dot<T, NH>(row, u2) : T(0);
+    ring[t & 1][q][lane] = f;
+    __syncthreads();
+    const T e = solve(2 * m + 1, t & 1);
+    if (has) {
+#pragma unroll
+      for (int j = 0; j < NH; ++j) acc2[j] = fmaT<T>(row[j], e, acc2[j]);
+    }
+  }
+
+  if (active) {
+#pragma unroll
+    for (int j = 0; j < NH; ++j) {
+      const T ev = tz == 0 ? acc1[j] : acc2[j];   // sums' (even) part
+      const T od = tz == 0 ? acc2[j] : acc1[j];   // differences' (odd) part
+      if (j < g.P) {
+        col[(long long)(g.base + j) * plane] = ev + od;
+        col[(long long)(g.n - 1 - j) * plane] = ev - od;
+      } else if (j == g.P && g.mid) {
+        col[(long long)g.c * plane] = ev;
+      }
+    }
+    if (g.base) col[0] = T(0);                    // DST-I: the wall slot
   }
 }
 
@@ -484,8 +623,12 @@ hipError_t run_a(const double* r, void* W, const BoxDev* boxes, const DomainDev*
 template <typename T, int NP>
 hipError_t run_b(void* W, const BoxDev* boxes, const int4* work, int nwork, const void* tab,
                  hipStream_t s) {
-  hipLaunchKernelGGL((k_pass_b<T, NP>), dim3(nwork), dim3(192), 0, s, (T*)W, boxes, work,
-                     (const T*)tab);
+  if constexpr (kPassBRing<T>)
+    hipLaunchKernelGGL((k_pass_b_ring<T, NP>), dim3(nwork), dim3(192), 0, s, (T*)W, boxes, work,
+                       (const T*)tab);
+  else
+    hipLaunchKernelGGL((k_pass_b<T, NP>), dim3(nwork), dim3(192), 0, s, (T*)W, boxes, work,
+                       (const T*)tab);
   return hipGetLastError();
 }
 template <typename T, int NP>
