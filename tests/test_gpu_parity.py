@@ -103,6 +103,8 @@ def test_stencil_two_domains():
     (96, 32, 2.0, 8, 3),               # size class 40: boxes {35, 38}
     (102, 34, 2.0, 6, 3),              # size class 40: boxes {37, 40}
     (84, 42, 8.0, 4, 3),               # size class 48: boxes of 45
+    (12, 4, 2.0, 4, 1),                # size class 8: boxes {5, 6}
+    (21, 7, 4.0, 3, 1),                # odd sides {8, 9}: classes 8 and 16 in one apply
 ])
 def test_precond_fp64_matches_oracle(n, sub, c, blk, overlap):
     P = problem(n, sub, c, blk, seed=n + sub)
