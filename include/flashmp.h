@@ -102,7 +102,7 @@ typedef struct {
 /* Krylov options.  solver: 0 = BiCGSTAB, 1 = flexible GMRES(restart).
  * rtol: stop when ||b - A x||_2 / ||b - A x0||_2 <= rtol (Sec. IV-A).
  * precond: 0 = none (identity), 1 = FlashMP RAS (+ learned part if set; the
- *   learned part is used by FGMRES only, judged per step by the FP64 residual:
+ *   learned part is used by FGMRES only, tested per step on the FP64 residual:
  *   a rejected step is recomputed with the plain preconditioner, and after
  *   three rejections in a row the rest of the solve runs without it).
  * check_every: host convergence check period for BiCGSTAB (>= 1).

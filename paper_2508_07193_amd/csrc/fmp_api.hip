@@ -35,7 +35,7 @@ constexpr int kScal = 256;      // doubles in the scalar area
 constexpr int kScalH = 16;      // h column of FGMRES
 constexpr int kScalW = 64;      // ||w||^2
 constexpr int kScalY = 128;     // FGMRES update coefficients
-constexpr int kScalJ = 200;     // learned-correction judge: ||v - w||^2, ||v - w + A d||^2
+constexpr int kScalJ = 200;     // learned-correction residual test: ||v - w||^2, ||v - w + A d||^2
 // per-group scalar block (kSD doubles per group)
 constexpr int kSD = 192;
 constexpr int kSDH = 0;         // h column and ||w||^2 before the update (<= 34)
@@ -265,7 +265,7 @@ static fmp_status spmv(fmp_ctx* h, const double* x, double* y, hipStream_t s) {
 // Learned part: defined in fmp_coarse.hip (returns the device correction
 // vector to add in pass C, or nullptr when the model is not set).
 fmp_status fmp_coarse_forward(fmp_ctx* h, const double* r, hipStream_t s, const double** out);
-hipError_t fmp_coarse_judge(fmp_ctx* h, const double* v, const double* w, double* partials,
+hipError_t fmp_coarse_resid_test(fmp_ctx* h, const double* v, const double* w, double* partials,
                             hipStream_t s);
 size_t fmp_coarse_workspace(int nsub, int hidden_max);
 void fmp_coarse_bind(fmp_ctx* h, void* base);
@@ -820,7 +820,7 @@ struct Ctx {
 };
 
 // z = M^{-1} r; the learned coarse correction is added only where the caller
-// can judge it (FGMRES), since BiCGSTAB assumes a fixed linear preconditioner.
+// can test it (FGMRES), since BiCGSTAB assumes a fixed linear preconditioner.
 fmp_status M_(Ctx& c, const double* r, double* z, bool learned);
 fmp_status M(Ctx& c, const double* r, double* z, bool learned = false) {
   hipEvent_t e = c.begin();
@@ -1121,7 +1121,7 @@ fmp_status fgmres(Ctx& c, const double* b, double* x, double* ws) {
     return FMP_OK;
   };
 
-  // the learned part stays on while the FP64 residual judge keeps accepting
+  // the learned part stays on while the FP64 residual test keeps accepting
   // it; after kMaxRejects rejections in a row the solve continues without it
   constexpr int kMaxRejects = 3;
   bool use_learned = !per && c.o->precond != 0 && h->learned_set;
@@ -1150,10 +1150,10 @@ fmp_status fgmres(Ctx& c, const double* b, double* x, double* ws) {
       if ((st = M(c, vj, zj, learned))) return st;
       if ((st = A(c, zj, w))) return st;
       if (learned) {
-        // the FP64 residual judges the correction: keep it only if
+        // the FP64 residual decides on the correction: keep it only if
         // ||v - A z|| does not exceed the plain preconditioner's ||v - A z_RAS||
         // (both sides carry the same basis scale)
-        HIPCHK(h, fmp_coarse_judge(h, vj, w, h->d_part, c.s));
+        HIPCHK(h, fmp_coarse_resid_test(h, vj, w, h->d_part, c.s));
         HIPCHK(h, launch_reduce(h->d_part, 2, h->d_S + kScalJ, 0, h->d_S, c.s));
         HIPCHK(h, hipMemcpyAsync(hs + kScalJ, h->d_S + kScalJ, 16, hipMemcpyDeviceToHost, c.s));
         HIPCHK(h, hipStreamSynchronize(c.s));

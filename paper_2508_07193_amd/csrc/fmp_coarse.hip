@@ -10,8 +10,8 @@
 // bf16 weights and FP32 accumulation.  Dividing by ||R0 r|| and multiplying
 // back makes the correction scale with r like a linear preconditioner.
 //
-// The FP64 residual judges the correction inside FGMRES: with v the
-// preconditioner input, z = z_RAS + d and w = A z, the kernel k_judge
+// The FP64 residual decides on the correction inside FGMRES: with v the
+// preconditioner input, z = z_RAS + d and w = A z, the kernel k_resid_test
 // compares ||v - w|| (with the correction) against ||v - w + A d|| (plain
 // RAS) in one pass over v and w, evaluating A d = d + c/eps K d on the fly
 // from the piecewise-constant d (K d vanishes inside a subdomain).  When the
@@ -118,7 +118,7 @@ __global__ __launch_bounds__(kT) void k_gemv(const __hip_bfloat16* __restrict__ 
   }
 }
 
-// ---------------------------------------------------------------- judge
+// ---------------------------------------------------------------- residual test
 // d(q, k, j, i): the piecewise-constant correction on unknown slots
 // v / d for 0 <= v < 2^20 from a precomputed float 1/d: the rounding error of
 // (v + 1/2) / d in FP32 stays far below its 1/(2d) margin to the next integer
@@ -182,7 +182,7 @@ __device__ double apply_A_at(const F& d, const DomainDev& D, const double* __res
 }
 
 // partials: [0] ||v - w||^2 (with the correction), [1] ||v - w + A d||^2 (plain)
-__global__ __launch_bounds__(kT) void k_judge(const double* __restrict__ v,
+__global__ __launch_bounds__(kT) void k_resid_test(const double* __restrict__ v,
                                               const double* __restrict__ w,
                                               const double* __restrict__ yc, int nsub,
                                               const DomainDev* __restrict__ doms, int ndom,
@@ -417,9 +417,9 @@ fmp_status fmp_coarse_forward(fmp_ctx* h, const double* r, hipStream_t s, const 
 }
 
 // one pass over v, w: partials of ||v - w||^2 and ||v - w + A d||^2
-hipError_t fmp_coarse_judge(fmp_ctx* h, const double* v, const double* w, double* partials,
+hipError_t fmp_coarse_resid_test(fmp_ctx* h, const double* v, const double* w, double* partials,
                             hipStream_t s) {
-  hipLaunchKernelGGL(k_judge, dim3(kRedBlocks), dim3(kT), 0, s, v, w, (const double*)h->d_yc,
+  hipLaunchKernelGGL(k_resid_test, dim3(kRedBlocks), dim3(kT), 0, s, v, w, (const double*)h->d_yc,
                      h->nsub, h->d_doms, (int)h->doms.size(), h->d_eps, h->len, partials);
   return hipGetLastError();
 }
