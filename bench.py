@@ -83,16 +83,17 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(P, iters, sample_boxes=512):
+def cpu_baseline(P, iters, sample_boxes=512, reps=4):
     """Time the CPU oracle on a bounded sample of one FGMRES iteration's work and scale it.
 
-    Sample: `sample_boxes` of the 512 subdomain solves (all of them by
-    default: one whole preconditioner apply), three sparse A x on a 64^3
-    sub-grid (scaled by unknown count), and ten dots and axpys on full 256^3
-    vectors (scaled to the CGS work of an average Arnoldi step, j = 15:
-    2j + 5 vector passes).  Reported as the estimated time-to-solution for the
-    same iteration count as the GPU run; `cores` is the BLAS thread count the
-    oracle's numpy calls use.
+    Sample: `reps` passes over `sample_boxes` of the 512 subdomain solves
+    (all of them by default: one whole preconditioner apply per pass), ten
+    sparse A x on a 64^3 sub-grid (scaled by unknown count), and twenty dots
+    and axpys on full 256^3 vectors (scaled to the CGS work of an average
+    Arnoldi step, j = 15: 2j + 5 vector passes); about 10-20 s of CPU work.
+    Reported as the estimated time-to-solution for the same iteration count
+    as the GPU run; `cores` is the BLAS thread count the oracle's numpy calls
+    use.
     """
     from oracle import ras, yee
     try:
@@ -105,32 +106,33 @@ def cpu_baseline(P, iters, sample_boxes=512):
     nsub = (n // P["sub"][0]) ** 3
     which = list(np.linspace(0, nsub - 1, sample_boxes).astype(int))
     t0 = time.perf_counter()
-    ras.ras_apply_subset(P["rhs"], P["c"], P["sub"], 1, eps_cell, which)
+    for _ in range(reps):
+        ras.ras_apply_subset(P["rhs"], P["c"], P["sub"], 1, eps_cell, which)
     m_pre = time.perf_counter() - t0
-    t_pre = m_pre * nsub / sample_boxes
+    t_pre = m_pre / reps * nsub / sample_boxes
     m = 64
     A = yee.assemble_A(m, m, m, P["c"], eps_cell[:m, :m, :m])
     xs = yee.from_padded(P["rhs"][:, :m, :m, :m])
     t0 = time.perf_counter()
-    for _ in range(3):
+    for _ in range(10):
         A @ xs
     m_spmv = time.perf_counter() - t0
-    t_spmv = m_spmv / 3 * (yee.n_unknowns(n, n, n) / xs.size)
+    t_spmv = m_spmv / 10 * (yee.n_unknowns(n, n, n) / xs.size)
     a = P["rhs"].ravel()
     b = np.roll(a, 1)
     t0 = time.perf_counter()
-    for _ in range(10):
+    for _ in range(20):
         float(np.dot(a, b))
         c = a + 0.5 * b
     m_vec = time.perf_counter() - t0
-    t_vec = m_vec / 20
+    t_vec = m_vec / 40
     del c
     per_it = t_pre + t_spmv + (2 * 15 + 5) * t_vec
     total = per_it * iters
     return dict(value=round(total * 1e3, 1), unit="ms", cores=cores, kind="oracle",
-                sample=(f"{sample_boxes}/{nsub} subdomain solves, three 64^3 sparse A x, ten dots "
-                        f"and axpys on 256^3 vectors, scaled to {iters} FGMRES iterations "
-                        f"({per_it * 1e3:.0f} ms per iteration)"),
+                sample=(f"{reps} x {sample_boxes}/{nsub} subdomain solves (a whole preconditioner "
+                        f"apply each), ten 64^3 sparse A x, twenty dots and axpys on 256^3 vectors, "
+                        f"scaled to {iters} FGMRES iterations ({per_it * 1e3:.0f} ms per iteration)"),
                 seconds_measured=round(m_pre + m_spmv + m_vec, 2))
 
 
