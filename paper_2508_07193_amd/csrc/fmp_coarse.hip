@@ -124,36 +124,52 @@ __global__ __launch_bounds__(kT) void k_gemv(const __hip_bfloat16* __restrict__ 
 // (v + 1/2) / d in FP32 stays far below its 1/(2d) margin to the next integer
 __device__ __forceinline__ int fquot(int v, float inv_d) { return (int)(((float)v + 0.5f) * inv_d); }
 
+// The field is evaluated around one centre slot (i0, j0, k0) at a time: the
+// centre's subdomain coordinates (si, sj, sk) and its position inside that
+// subdomain (li, lj, lk) are computed once, and a neighbour one cell away
+// lies in the same subdomain or the next one along that axis (subdomains
+// have equal sides within a domain).
 struct CoarseField {
   const double* yc;
   int nsub;
   DomainDev D;
-  float inv_sx, inv_sy, inv_sz;
+  int i0, j0, k0;
+  int si, sj, sk, li, lj, lk;
+  // branch-free, so that the loads of all stencil terms are issued together:
+  // a slot outside the domain or on a wall reads a clamped in-range entry
+  // and yields 0
   __device__ __forceinline__ double operator()(int q, int k, int j, int i) const {
-    if (i < 0 || j < 0 || k < 0 || i >= D.nx || j >= D.ny || k >= D.nz) return 0.0;
-    if (is_wall(q, i, j, k)) return 0.0;
-    const int s = D.sub0 + (fquot(k, inv_sz) * D.py + fquot(j, inv_sy)) * D.px + fquot(i, inv_sx);
-    return yc[(long long)q * nsub + s];
+    const bool ok = i >= 0 && j >= 0 && k >= 0 && i < D.nx && j < D.ny && k < D.nz &&
+                    !is_wall(q, i, j, k);
+    const int ai = li + (i - i0), aj = lj + (j - j0), ak = lk + (k - k0);
+    const int ti = min(max(si + (ai < 0 ? -1 : (ai >= D.sx ? 1 : 0)), 0), D.px - 1);
+    const int tj = min(max(sj + (aj < 0 ? -1 : (aj >= D.sy ? 1 : 0)), 0), D.py - 1);
+    const int tk = min(max(sk + (ak < 0 ? -1 : (ak >= D.sz ? 1 : 0)), 0), D.pz - 1);
+    const double v = yc[(long long)q * nsub + D.sub0 + (tk * D.py + tj) * D.px + ti];
+    return ok ? v : 0.0;
   }
 };
 
-__device__ __forceinline__ double cell_eps(const double* __restrict__ e, const DomainDev& D, int i,
-                                           int j, int k) {
-  const int b = D.eps_b;
-  return e[D.eps_off + ((k / b) * D.eps_nby + (j / b)) * D.eps_nbx + (i / b)];
+// cell permittivity; the block index comes from a reciprocal of the block
+// side (coordinates are non-negative and below 2^20)
+__device__ __forceinline__ double cell_eps(const double* __restrict__ e, const DomainDev& D,
+                                           float inv_b, int i, int j, int k) {
+  return e[D.eps_off + (fquot(k, inv_b) * D.eps_nby + fquot(j, inv_b)) * D.eps_nbx +
+           fquot(i, inv_b)];
 }
 
-// (A d) at slot (q, k, j, i), the same 13-point double-curl as the stencil kernel
-template <class F>
-__device__ double apply_A_at(const F& d, const DomainDev& D, const double* __restrict__ eps, int q,
-                             int k, int j, int i) {
+// (A d) at slot (q, k, j, i), the same 13-point double-curl as the stencil
+// kernel.  Away from subdomain faces and the walls K d = 0 exactly, so the
+// slot's own value is returned; the face slots of a wave (a few lanes of each
+// 64-slot row) take the full stencil, whose neighbour lookups are cheap.
+__device__ double apply_A_at(const CoarseField& d, const DomainDev& D,
+                             const double* __restrict__ eps, float inv_b, int q, int k, int j,
+                             int i) {
   if (is_wall(q, i, j, k)) return 0.0;
   const double c0 = d(q, k, j, i);
-  // interior of a subdomain, away from walls: K d = 0
-  const int li = i - fquot(i, d.inv_sx) * D.sx, lj = j - fquot(j, d.inv_sy) * D.sy;
-  const int lk = k - fquot(k, d.inv_sz) * D.sz;
-  if (li >= 1 && li + 1 < D.sx && lj >= 1 && lj + 1 < D.sy && lk >= 1 && lk + 1 < D.sz &&
-      i >= 2 && j >= 2 && k >= 2 && i + 2 < D.nx && j + 2 < D.ny && k + 2 < D.nz)
+  if (d.li >= 1 && d.li + 1 < D.sx && d.lj >= 1 && d.lj + 1 < D.sy && d.lk >= 1 &&
+      d.lk + 1 < D.sz && i >= 2 && j >= 2 && k >= 2 && i + 2 < D.nx && j + 2 < D.ny &&
+      k + 2 < D.nz)
     return c0;
   double kd, sc = D.c;
   if (q == 0) {
@@ -161,22 +177,28 @@ __device__ double apply_A_at(const F& d, const DomainDev& D, const double* __res
          (d(1, k, j, i + 1) - d(1, k, j, i) - d(1, k, j - 1, i + 1) + d(1, k, j - 1, i)) +
          (d(2, k, j, i + 1) - d(2, k, j, i) - d(2, k - 1, j, i + 1) + d(2, k - 1, j, i));
     if (D.eps_b > 0)
-      sc = D.c / (0.25 * (((cell_eps(eps, D, i, j - 1, k - 1) + cell_eps(eps, D, i, j - 1, k)) +
-                           cell_eps(eps, D, i, j, k - 1)) + cell_eps(eps, D, i, j, k)));
+      sc = D.c / (0.25 * (((cell_eps(eps, D, inv_b, i, j - 1, k - 1) +
+                            cell_eps(eps, D, inv_b, i, j - 1, k)) +
+                           cell_eps(eps, D, inv_b, i, j, k - 1)) +
+                          cell_eps(eps, D, inv_b, i, j, k)));
   } else if (q == 1) {
     kd = 4.0 * c0 - d(1, k + 1, j, i) - d(1, k - 1, j, i) - d(1, k, j, i + 1) - d(1, k, j, i - 1) +
          (d(2, k, j + 1, i) - d(2, k, j, i) - d(2, k - 1, j + 1, i) + d(2, k - 1, j, i)) +
          (d(0, k, j + 1, i) - d(0, k, j, i) - d(0, k, j + 1, i - 1) + d(0, k, j, i - 1));
     if (D.eps_b > 0)
-      sc = D.c / (0.25 * (((cell_eps(eps, D, i - 1, j, k - 1) + cell_eps(eps, D, i - 1, j, k)) +
-                           cell_eps(eps, D, i, j, k - 1)) + cell_eps(eps, D, i, j, k)));
+      sc = D.c / (0.25 * (((cell_eps(eps, D, inv_b, i - 1, j, k - 1) +
+                            cell_eps(eps, D, inv_b, i - 1, j, k)) +
+                           cell_eps(eps, D, inv_b, i, j, k - 1)) +
+                          cell_eps(eps, D, inv_b, i, j, k)));
   } else {
     kd = 4.0 * c0 - d(2, k, j, i + 1) - d(2, k, j, i - 1) - d(2, k, j + 1, i) - d(2, k, j - 1, i) +
          (d(0, k + 1, j, i) - d(0, k, j, i) - d(0, k + 1, j, i - 1) + d(0, k, j, i - 1)) +
          (d(1, k + 1, j, i) - d(1, k, j, i) - d(1, k + 1, j - 1, i) + d(1, k, j - 1, i));
     if (D.eps_b > 0)
-      sc = D.c / (0.25 * (((cell_eps(eps, D, i - 1, j - 1, k) + cell_eps(eps, D, i - 1, j, k)) +
-                           cell_eps(eps, D, i, j - 1, k)) + cell_eps(eps, D, i, j, k)));
+      sc = D.c / (0.25 * (((cell_eps(eps, D, inv_b, i - 1, j - 1, k) +
+                            cell_eps(eps, D, inv_b, i - 1, j, k)) +
+                           cell_eps(eps, D, inv_b, i, j - 1, k)) +
+                          cell_eps(eps, D, inv_b, i, j, k)));
   }
   return c0 + sc * kd;
 }
@@ -200,7 +222,7 @@ __global__ __launch_bounds__(kT) void k_resid_test(const double* __restrict__ v,
   int pl = 1;
   double inv_cs = 1.0, inv_pl = 1.0;
   double inv_nx = 1.0;
-  float inv_sx = 1.f, inv_sy = 1.f, inv_sz = 1.f;
+  float inv_sx = 1.f, inv_sy = 1.f, inv_sz = 1.f, inv_b = 1.f;
   for (long long e = (long long)blockIdx.x * kT + threadIdx.x; e < len; e += stride) {
     int dn = d < 0 ? 0 : d;
     while (dn + 1 < ndom && e >= doms[dn + 1].offset) ++dn;
@@ -215,6 +237,7 @@ __global__ __launch_bounds__(kT) void k_resid_test(const double* __restrict__ v,
       inv_sx = 1.f / (float)D.sx;
       inv_sy = 1.f / (float)D.sy;
       inv_sz = 1.f / (float)D.sz;
+      inv_b = D.eps_b > 0 ? 1.f / (float)D.eps_b : 1.f;
     }
     const long long loc = e - D.offset;
     const int q = (int)(((double)loc + 0.5) * inv_cs);
@@ -222,8 +245,10 @@ __global__ __launch_bounds__(kT) void k_resid_test(const double* __restrict__ v,
     const int k = (int)(((double)rem + 0.5) * inv_pl);
     const int rr = (int)(rem - (long long)k * pl);
     const int j = (int)(((double)rr + 0.5) * inv_nx), i = rr - j * D.nx;
-    const CoarseField F{yc, nsub, D, inv_sx, inv_sy, inv_sz};
-    const double ad = apply_A_at(F, D, eps, q, k, j, i);
+    const int si = fquot(i, inv_sx), sj = fquot(j, inv_sy), sk = fquot(k, inv_sz);
+    const CoarseField F{yc, nsub, D, i, j, k, si, sj, sk,
+                        i - si * D.sx, j - sj * D.sy, k - sk * D.sz};
+    const double ad = apply_A_at(F, D, eps, inv_b, q, k, j, i);
     const double rl = v[e] - w[e];
     const double rp = rl + ad;
     a0 = __builtin_fma(rl, rl, a0);
