@@ -140,6 +140,8 @@ def rel2(a, b):
 # 2-norm relative error of at most about 2u (the transforms are orthogonal and
 # the 3x3 solve is a contraction, ||B^-1|| <= 1).  Bound: 12u.
 @pytest.mark.parametrize("n,sub,blk,overlap", [
+    (12, 4, 4, 1),                     # size class 8: boxes {5, 6}
+    (21, 7, 3, 1),                     # odd sides {8, 9}: classes 8 and 16
     (48, 16, 8, 1),                    # size class 24
     (96, 32, 8, 3),                    # size class 40
     (84, 42, 4, 3),                    # size class 48
