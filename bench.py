@@ -96,11 +96,7 @@ def cpu_baseline(P, iters, sample_boxes=512, reps=4):
     use.
     """
     from oracle import ras, yee
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    except Exception:
-        cores = os.cpu_count()
+    cores = blas_threads()
     n = P["nx"]
     eps_cell = yee.expand_eps(P["eps"], P["eps_block"], n, n, n)
     nsub = (n // P["sub"][0]) ** 3
@@ -129,11 +125,126 @@ def cpu_baseline(P, iters, sample_boxes=512, reps=4):
     del c
     per_it = t_pre + t_spmv + (2 * 15 + 5) * t_vec
     total = per_it * iters
-    return dict(value=round(total * 1e3, 1), unit="ms", cores=cores, kind="oracle",
-                sample=(f"{reps} x {sample_boxes}/{nsub} subdomain solves (a whole preconditioner "
-                        f"apply each), ten 64^3 sparse A x, twenty dots and axpys on 256^3 vectors, "
-                        f"scaled to {iters} FGMRES iterations ({per_it * 1e3:.0f} ms per iteration)"),
-                seconds_measured=round(m_pre + m_spmv + m_vec, 2))
+    out = dict(value=round(total * 1e3, 1), unit="ms", cores=cores, kind="oracle",
+               sample=(f"{reps} x {sample_boxes}/{nsub} subdomain solves (a whole preconditioner "
+                       f"apply each), ten 64^3 sparse A x, twenty dots and axpys on 256^3 vectors, "
+                       f"scaled to {iters} FGMRES iterations ({per_it * 1e3:.0f} ms per iteration); "
+                       f"the whole 128^3 solve is measured end to end in cpu_oracle_c2"),
+               seconds_measured=round(m_pre + m_spmv + m_vec, 2))
+    out.update(cpu_info())
+    return out
+
+
+def cpu_info():
+    """Host CPU model (from /proc/cpuinfo) and the logical CPUs this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except AttributeError:
+        ncpu = os.cpu_count()
+    return dict(cpu_model=model, nproc=ncpu)
+
+
+def blas_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        return os.cpu_count()
+
+
+def cpu_oracle_c2():
+    """The CPU oracle's full solve of the 128^3 workload, measured end to end:
+    sparse assembly of A, then right-preconditioned BiCGSTAB in FP64 to 1e-8
+    with the oracle's RAS (every subdomain solved by the transform route of
+    oracle.transforms).  Returns the timings and the solution (padded)."""
+    from oracle import krylov, ras, yee
+    from paper_2508_07193_amd import inputs
+    P = inputs.make_problem("c2")
+    n = P["nx"]
+    eps_cell = yee.expand_eps(P["eps"], P["eps_block"], n, n, n)
+    t0 = time.perf_counter()
+    A = yee.assemble_A(n, n, n, P["c"], eps_cell)
+    t_asm = time.perf_counter() - t0
+
+    def Aop(v):
+        return yee.to_padded(A @ yee.from_padded(v), n, n, n)
+
+    def Mop(v):
+        return ras.ras_apply(v, P["c"], P["sub"], 1, eps_cell)
+    t0 = time.perf_counter()
+    x, info = krylov.bicgstab(Aop, P["rhs"], M=Mop, tol=P["tol"], maxiter=500)
+    t_solve = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    Mop(P["rhs"])
+    t_pre = time.perf_counter() - t0
+    out = dict(kind="oracle", measured="whole solve", time_to_solution_s=round(t_solve, 2),
+               assembly_s=round(t_asm, 2), iterations=int(info["iterations"]),
+               rel_residual_true=float(info["rel_true"]),
+               precond_applies_per_s=round(1.0 / t_pre, 3), threads=blas_threads(),
+               workload="128^3, 4^3 subdomains of 32^3 (overlap 1), eps_r U[1,10] on 8^3 cubes, "
+                        "c=2, RHS N(0,1) seed 2; BiCGSTAB FP64 to 1e-8 (CPU oracle, NumPy/SciPy)")
+    out.update(cpu_info())
+    return out, x
+
+
+def c2_leg(args, dev, log):
+    """128^3 workload (4^3 subdomains of 32^3, eps_r U[1,10] on 8^3 cubes, c = 2,
+    seed 2): BiCGSTAB in FP64 to 1e-8 with the FP64 FlashMP RAS (the configured
+    solver), and FGMRES(30) in FP64 with FP32 and BF16 transforms on the same
+    grid.  Solutions are written to args.c2_dir for the comparison with the CPU
+    oracle's solution in the parent process."""
+    import torch
+    from paper_2508_07193_amd import api, inputs
+    P = inputs.make_problem("c2")
+    n = P["nx"]
+    dom = dict(nx=n, ny=n, nz=n, c=P["c"], eps=P["eps"], eps_block=P["eps_block"], sub=P["sub"])
+    b = torch.from_numpy(P["rhs"].ravel()).to(dev)
+    res = {}
+    for prec, solver in (("fp64", "bicgstab"), ("fp32", "fgmres"), ("bf16", "fgmres")):
+        h = api.Handle([dom], overlap=1, precision=prec, device=dev, use_graph=args.graphs,
+                       batch_boxes=-1)
+        h.autotune(b)
+        x = h.new_vector()
+        kw = dict(solver=solver, rtol=P["tol"], max_iter=500)
+        for _ in range(max(1, args.warmup)):
+            x.zero_()
+            h.solve(b, x, **kw)
+        times = []
+        for _ in range(max(1, args.steps)):
+            x.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = h.solve(b, x, **kw)
+            torch.cuda.synchronize()
+            times.append((time.perf_counter() - t0) * 1e3)
+        z = h.new_vector()
+        h.apply_precond(b, z)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(20):
+            h.apply_precond(b, z)
+        torch.cuda.synchronize()
+        t_pre = (time.perf_counter() - t0) / 20 * 1e3
+        if args.c2_dir:
+            np.save(os.path.join(args.c2_dir, f"x_{prec}.npy"), x.cpu().numpy())
+        res[prec] = dict(solver=solver, transforms=prec, time_to_solution_ms=round(float(np.mean(times)), 2),
+                         iterations=info["iterations"], rel_residual_true=info["rel_residual_true"],
+                         n_precond=info["n_precond"], n_spmv=info["n_spmv"],
+                         precond_ms=round(t_pre, 4), precond_applies_per_s=round(1e3 / t_pre, 1))
+        log(f"[c2] {prec} {solver}: {res[prec]}")
+        h.close()
+    return dict(workload="128^3 Yee grid, PEC walls, 4^3 subdomains of 32^3 (overlap 1), eps_r "
+                         "U[1,10] on 8^3 cubes, c=2, RHS N(0,1) seed 2; FP64 Krylov to 1e-8",
+                runs=res)
 
 
 def learned_leg(args, dev, log):
@@ -148,7 +259,7 @@ def learned_leg(args, dev, log):
     n = P["nx"]
     dom = dict(nx=n, ny=n, nz=n, c=P["c"], eps=P["eps"], eps_block=P["eps_block"], sub=P["sub"])
     h = api.Handle([dom], overlap=1, precision="fp64", use_learned=True, device=dev,
-                   batch_boxes=-1, use_graph=False)
+                   batch_boxes=-1, use_graph=args.graphs)
     h.autotune()
     t0 = time.perf_counter()
     X, Y = learned.generate_pairs(h, (n, n, n), args.pairs_rhs, args.pairs_per_rhs, 1005, log=log)
@@ -446,12 +557,12 @@ def c3_context(args):
 
     def tuned_handle(prec):
         hh = api.Handle([dom], overlap=1, precision=prec, device=dev, batch_boxes=-1,
-                        use_graph=False)
+                        use_graph=args.graphs)
         t = hh.autotune(b)
         c = [e for e in t if e["chosen"]][0]
         log(f"[{prec}] autotune: {[(e['batch_boxes'], e['streams'], e['slab_order'], round(e['apply_ms'], 4)) for e in t]}")
         return hh, dict(batch_boxes=c["batch_boxes"], streams=c["streams"], slab_order=c["slab_order"],
-                        graph=False)
+                        graph=bool(args.graphs))
 
     return dict(torch=torch, P=P, b=b, n_unk=n_unk, run_solves=run_solves,
                 time_events=time_events, tuned_handle=tuned_handle)
@@ -563,7 +674,7 @@ def variant_leg(args):
     return out
 
 
-def run_leg(args):
+def run_leg(args, emit=True):
     dev = "cuda:0"
     if args.leg == "main":
         res = main_leg(args)
@@ -579,20 +690,31 @@ def run_leg(args):
         res = cn_leg(args, dev, log)
     elif args.leg == "whole":
         res = whole_leg(args, dev, log)
+    elif args.leg == "c2":
+        res = c2_leg(args, dev, log)
     else:
         raise SystemExit(f"unknown leg {args.leg}")
-    print("LEG_RESULT " + json.dumps(res), flush=True)
+    if emit:
+        print("LEG_RESULT " + json.dumps(res), flush=True)
+    return res
 
 
 def child(args, leg, extra=()):
-    """Run one leg in a child process (each leg gets a fresh process and one
-    handle); its progress goes to our stderr, its result comes back as JSON."""
+    """Run one leg in a child process (each leg gets a fresh process), or in this
+    process with --isolate 0; progress goes to stderr, the result comes back as
+    JSON."""
     import subprocess
-    cmd = [sys.executable, "-u", os.path.abspath(__file__), "--leg", leg,
-           "--steps", str(args.steps), "--warmup", str(args.warmup), "--config", args.config,
-           "--pairs-rhs", str(args.pairs_rhs), "--pairs-per-rhs", str(args.pairs_per_rhs),
-           "--epochs", str(args.epochs)] + list(extra)
+    opts = ["--steps", str(args.steps), "--warmup", str(args.warmup), "--config", args.config,
+            "--pairs-rhs", str(args.pairs_rhs), "--pairs-per-rhs", str(args.pairs_per_rhs),
+            "--epochs", str(args.epochs), "--graphs", str(args.graphs)] + list(extra)
     log(f"[bench] leg {leg} {' '.join(extra)}")
+    if not args.isolate:
+        sub = parse_args(["--leg", leg] + opts)
+        t0 = time.perf_counter()
+        res = run_leg(sub, emit=False)
+        log(f"[bench] leg {leg} done in {time.perf_counter() - t0:.1f} s")
+        return res
+    cmd = [sys.executable, "-u", os.path.abspath(__file__), "--leg", leg] + opts
     p = subprocess.run(cmd, stdout=subprocess.PIPE, text=True)
     for line in p.stdout.splitlines():
         if line.startswith("LEG_RESULT "):
@@ -600,7 +722,7 @@ def child(args, leg, extra=()):
     return dict(error=f"leg {leg} ended with status {p.returncode} and no result")
 
 
-def main():
+def parse_args(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
@@ -621,7 +743,18 @@ def main():
     ap.add_argument("--prec", default=None, help=argparse.SUPPRESS)
     ap.add_argument("--ref-out", default=None, help=argparse.SUPPRESS)
     ap.add_argument("--ref-in", default=None, help=argparse.SUPPRESS)
-    args = ap.parse_args()
+    ap.add_argument("--c2", type=int, default=1,
+                    help="run the 128^3 leg (GPU solves compared with the CPU oracle's solve)")
+    ap.add_argument("--c2-dir", default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--graphs", type=int, default=1,
+                    help="capture preconditioner applies in hipGraphs in every leg")
+    ap.add_argument("--isolate", type=int, default=1,
+                    help="1: every leg in a child process of its own; 0: all legs in this process")
+    return ap.parse_args(argv)
+
+
+def main():
+    args = parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the solver has no multi-GPU path; "
               "its kernels run one GPU's share of a sharded grid at its real shape",
@@ -631,9 +764,10 @@ def main():
         run_leg(args)
         return
 
-    # This process never touches the GPU: each leg runs in a child process of
-    # its own and reports back, so one leg's failure is reported as that leg's
-    # error instead of ending the whole run.
+    # By default this process never touches the GPU: each leg runs in a child
+    # process of its own and reports back, so one leg's failure is reported as
+    # that leg's error instead of ending the whole run (--isolate 0 runs every
+    # leg in this process, one after the other).
     import shutil
     import tempfile
     tmp = tempfile.mkdtemp(prefix="fmp_bench_")
@@ -658,11 +792,32 @@ def main():
             out["variants"]["convergence_overlap"] = child(args, "convergence")
         if args.cn:
             out["variants"]["cn_time_stepping"] = child(args, "cn")
+        if args.c2:
+            c2dir = os.path.join(tmp, "c2")
+            os.makedirs(c2dir, exist_ok=True)
+            out["variants"]["c2"] = child(args, "c2", ["--c2-dir", c2dir])
+        # CPU work only after every GPU leg, so it never competes with them
+        if not args.no_cpu:
+            from paper_2508_07193_amd import inputs
+            out["cpu_baseline"] = cpu_baseline(inputs.make_problem(args.config), out["iterations"])
+            if args.c2 and "runs" in out["variants"]["c2"]:
+                log("[bench] CPU oracle: whole 128^3 BiCGSTAB solve")
+                oc2, xo = cpu_oracle_c2()
+                out["cpu_oracle_c2"] = oc2
+                c2 = out["variants"]["c2"]
+                xo = xo.ravel()
+                for prec, r in c2["runs"].items():
+                    f = os.path.join(c2dir, f"x_{prec}.npy")
+                    if os.path.exists(f):
+                        xg = np.load(f)
+                        r["rel_err_vs_oracle_solution"] = float(np.linalg.norm(xg - xo) / np.linalg.norm(xo))
+                r64 = c2["runs"].get("fp64", {})
+                if "time_to_solution_ms" in r64:
+                    c2["speedup_vs_cpu_oracle"] = round(oc2["time_to_solution_s"] * 1e3 /
+                                                        r64["time_to_solution_ms"], 1)
+                log(f"[bench] CPU oracle 128^3: {oc2}")
     finally:
         shutil.rmtree(tmp, ignore_errors=True)
-    if not args.no_cpu:
-        from paper_2508_07193_amd import inputs
-        out["cpu_baseline"] = cpu_baseline(inputs.make_problem(args.config), out["iterations"])
     print(json.dumps(out), flush=True)
 
 

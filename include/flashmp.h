@@ -153,7 +153,13 @@ typedef struct {
   int32_t n_orth_dot, n_orth_update;
 } fmp_solve_info;
 
-/* Build the subdomain plans for n_domains independent domains.
+/* Build the subdomain plans for n_domains independent domains: the overlapping
+ * decomposition of Sec. II-B (each owned block extended by the overlap gamma
+ * into the box of the restriction S_i^gamma, clipped at the PEC walls; the
+ * owned block is what the prolongation S_i^0T writes back), the per-box
+ * constant alpha_s = c / (mean eps_r over the owned cells) of the subdomain
+ * operator (eq. (7) with a subdomain-constant permittivity) and the transform
+ * tables of Sec. III-A for every box side.
  * Two-phase: with ws == NULL, writes the workspace size to *ws_bytes and
  * returns FMP_OK with *out = NULL.  Then call again with a device buffer of
  * at least *ws_bytes bytes (256-byte aligned) to get a handle in *out.
@@ -206,7 +212,11 @@ fmp_status fmp_autotune(fmp_handle h, const double* r, double* z, fmp_tune_entry
 /* Workspace the solver needs for `opts` (bytes).  */
 fmp_status fmp_solve_workspace(fmp_handle h, const fmp_solve_opts* opts, size_t* bytes);
 
-/* Solve A x = b.  x holds the initial guess on entry and the solution on
+/* Solve A x = b (eq. (7)) with the Krylov methods of Sec. IV-A: BiCGSTAB or
+ * GMRES(restart) (flexible, right-preconditioned by fmp_apply_precond), stopped
+ * when the recomputed FP64 residual meets rtol; per iteration BiCGSTAB does two
+ * preconditioner applies and two operator applies, GMRES one of each plus the
+ * orthogonalisation (Table III).  x holds the initial guess on entry and the solution on
  * exit; the wall slots of b and of the initial x are ignored, and those of x
  * are 0 on exit.  ws: device buffer of fmp_solve_workspace bytes (256-byte
  * aligned).  Returns FMP_OK, FMP_NOT_CONVERGED (x = last iterate), or
@@ -289,9 +299,22 @@ size_t fmp_mlp_scratch_bytes(int32_t in_dim, int32_t hidden, int32_t batch);
 fmp_status fmp_mlp_adam(int32_t n_params, float* params, const float* grads, float* m, float* v,
                         int32_t t, float lr, void* stream);
 
+/* Release a handle.  Synchronises the device first (captured applies may
+ * still replay on any stream), then frees the handle's graphs, private
+ * streams, events and pinned host mirrors.  The caller's workspace is not
+ * touched.  FMP_ERR_HIP if the synchronisation reported an error (the handle
+ * is released either way). */
 fmp_status fmp_destroy(fmp_handle h);
 const char* fmp_status_string(fmp_status st);
 const char* fmp_last_error(fmp_handle h);
+
+/* HIP versions in the HIP_VERSION encoding (major * 10^7 + minor * 10^5 +
+ * patch): *compiled = the headers the library was built with, *running = the
+ * libamdhip64 the process has loaded (a framework may bundle an older one of
+ * the same major release; 0 if it cannot be queried).  fmp_setup_subdomains
+ * refuses a runtime of another major release with FMP_ERR_UNSUPPORTED.
+ * Host only; FMP_ERR_HIP if the runtime cannot be queried. */
+fmp_status fmp_runtime_version(int32_t* compiled, int32_t* running);
 
 #ifdef __cplusplus
 }

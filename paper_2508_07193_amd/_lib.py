@@ -15,7 +15,7 @@ EXPORTS = ["fmp_setup_subdomains", "fmp_vector_layout", "fmp_curlcurl_apply", "f
            "fmp_autotune", "fmp_solve_workspace", "fmp_solve", "fmp_curl_e", "fmp_curl_h",
            "fmp_cn_workspace", "fmp_cn_step", "fmp_coarse_size", "fmp_set_coarse_model",
            "fmp_coarse_restrict", "fmp_mlp_loss_grad", "fmp_mlp_scratch_bytes", "fmp_mlp_adam",
-           "fmp_destroy", "fmp_status_string", "fmp_last_error"]
+           "fmp_destroy", "fmp_status_string", "fmp_last_error", "fmp_runtime_version"]
 
 
 class DomainDesc(C.Structure):
@@ -89,6 +89,7 @@ def load():
     L.fmp_status_string.restype = C.c_char_p
     L.fmp_last_error.argtypes = [vp]
     L.fmp_last_error.restype = C.c_char_p
+    L.fmp_runtime_version.argtypes = [C.POINTER(i32), C.POINTER(i32)]
     for name in EXPORTS:
         f = getattr(L, name)
         if name not in ("fmp_mlp_scratch_bytes", "fmp_status_string", "fmp_last_error"):

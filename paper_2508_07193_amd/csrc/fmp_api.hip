@@ -288,6 +288,15 @@ const char* fmp_status_string(fmp_status st) {
 
 const char* fmp_last_error(fmp_handle h) { return h ? h->err.c_str() : "null handle"; }
 
+fmp_status fmp_runtime_version(int32_t* compiled, int32_t* running) {
+  if (!compiled || !running) return FMP_ERR_INVALID_ARG;
+  *compiled = HIP_VERSION;
+  int rt = 0;
+  const hipError_t e = hipRuntimeGetVersion(&rt);
+  *running = e == hipSuccess ? rt : 0;
+  return e == hipSuccess ? FMP_OK : FMP_ERR_HIP;
+}
+
 fmp_status fmp_setup_subdomains(const fmp_domain_desc* domains, int32_t n_domains,
                                 const fmp_precond_desc* pd, void* ws, size_t* ws_bytes,
                                 void* stream, fmp_handle* out) {
@@ -557,6 +566,16 @@ fmp_status fmp_setup_subdomains(const fmp_domain_desc* domains, int32_t n_domain
     *ws_bytes = need;
     return FMP_OK;
   }
+  // The library is built against one HIP release and runs on whichever
+  // libamdhip64 the process loaded first (a framework may bundle its own).
+  // A different major release changes the runtime ABI: refuse it here rather
+  // than fail somewhere inside a launch.
+  int rt = 0;
+  if (hipRuntimeGetVersion(&rt) != hipSuccess || rt / 10000000 != HIP_VERSION_MAJOR) {
+    h->err = "HIP runtime " + std::to_string(rt) + " does not match the major release of the "
+             "headers the library was built with (" + std::to_string(HIP_VERSION) + ")";
+    return FMP_ERR_UNSUPPORTED;
+  }
   if (*ws_bytes < need) return FMP_ERR_WORKSPACE;
   if (((uintptr_t)ws) % kAlign) return FMP_ERR_WORKSPACE;
   if (!out) return FMP_ERR_INVALID_ARG;
@@ -635,9 +654,14 @@ fmp_status fmp_vector_layout(fmp_handle h, int64_t* offsets) {
 
 fmp_status fmp_destroy(fmp_handle h) {
   if (!h) return FMP_ERR_INVALID_ARG;
+  // Graph replays of this handle may still run on any stream a caller passed;
+  // every executable graph, private stream, event and pinned mirror is
+  // released only once the device has drained them.
+  const hipError_t sync = hipDeviceSynchronize();
+  for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.exec);
+  h->graphs.clear();
   if (h->h_S) (void)hipHostFree(h->h_S);
   if (h->h_SD) (void)hipHostFree(h->h_SD);
-  for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.exec);
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   for (int i = 0; i < fmp_ctx::kMaxStreams; ++i) {
     if (h->bat_stream[i]) (void)hipStreamDestroy(h->bat_stream[i]);
@@ -645,7 +669,7 @@ fmp_status fmp_destroy(fmp_handle h) {
   }
   if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
   delete h;
-  return FMP_OK;
+  return sync == hipSuccess ? FMP_OK : FMP_ERR_HIP;
 }
 
 fmp_status fmp_curlcurl_apply(fmp_handle h, const double* x, double* y, void* stream) {
@@ -695,8 +719,13 @@ fmp_status fmp_autotune(fmp_handle h, const double* r, double* z, fmp_tune_entry
   HIPCHK(h, hipEventCreate(&e1));
   const double* coarse = nullptr;   // the learned part does not depend on the plan
   auto use = [&](int b, int ns, int so) -> fmp_status {
-    for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.exec);
-    h->graphs.clear();
+    // a captured apply may still be replaying on some caller stream: drain
+    // the device before its executable graph is released
+    if (!h->graphs.empty()) {
+      HIPCHK(h, hipDeviceSynchronize());
+      for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.exec);
+      h->graphs.clear();
+    }
     h->slab_order = so;
     plan_batches(h, b);
     h->nstreams = ns;

@@ -4,8 +4,9 @@ covering a 64³ or 96³ domain) make the preconditioner the exact inverse up to
 bf16 rounding, so FGMRES converges in a few steps.
 
 Tolerance: as for the smaller classes, each of the six bf16 contraction
-stages adds at most about 2u (u = 2^-8) of 2-norm relative error and the 3x3
-solve is a contraction: 12u."""
+stages adds at most about 2u (u = 2^-8) of its input's 2-norm and the 3x3
+solve is a contraction: box by box, the owned block's error is below 12u
+times the 2-norm of the box's restricted input."""
 import numpy as np
 import pytest
 import torch
@@ -49,9 +50,16 @@ def test_bf16_large_boxes_within_bound(n, sub, blk, overlap):
     h.apply_precond(dev(P["rhs"]), z)
     ref = ras.ras_apply(P["rhs"], 2.0, P["sub"], overlap, eps_cell)
     out = host(z, ref.shape)
-    err = rel2(out, ref)
-    print(f"n={n} sub={sub} overlap={overlap}: 2-norm rel err {err:.3e} (bound {12 * U_BF16:.3e})")
-    assert err < 12 * U_BF16
+    errs = []
+    for idx, s in enumerate(ras.subdomains(n, n, n, P["sub"], overlap)):
+        (x0, x1), (y0, y1), (z0, z1) = s["own"]
+        (bx0, bx1), (by0, by1), (bz0, bz1) = s["box"]
+        rin = np.linalg.norm(yee.from_padded(P["rhs"][:, bz0:bz1, by0:by1, bx0:bx1]))
+        d = (out - ref)[:, z0:z1, y0:y1, x0:x1]
+        errs.append(np.linalg.norm(d.ravel()) / rin)
+    print(f"n={n} sub={sub} overlap={overlap}: worst box error {max(errs):.3e} "
+          f"(bound {12 * U_BF16:.3e}), whole vector {rel2(out, ref):.3e}")
+    assert max(errs) < 12 * U_BF16
     assert np.all(out[~inputs.unknown_slots(n, n, n)] == 0.0)
 
 

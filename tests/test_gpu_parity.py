@@ -137,8 +137,24 @@ def rel2(a, b):
 
 # Reduced precision: each of the six contractions rounds its inputs and the
 # table entries (unit roundoff u: 2^-24 FP32, 2^-8 bf16), so each stage adds a
-# 2-norm relative error of at most about 2u (the transforms are orthogonal and
-# the 3x3 solve is a contraction, ||B^-1|| <= 1).  Bound: 12u.
+# 2-norm error of at most about 2u of its input's norm (the transforms are
+# orthogonal and the 3x3 solve is a contraction, ||B^-1|| <= 1).  Bound, box by
+# box: ||z_own - z_own_exact||_2 <= 12u ||S^gamma r||_2, the owned block's
+# error against the norm of that box's restricted input.  A whole-vector norm
+# would hide a box face that is wrong by O(1); a per-box one does not.
+def per_box_errors(out, ref, rhs, sub, overlap):
+    """[(subdomain, ||out - ref||_2 on its owned block / ||S^gamma rhs||_2)]."""
+    _, nz, ny, nx = rhs.shape
+    errs = []
+    for idx, s in enumerate(ras.subdomains(nx, ny, nz, sub, overlap)):
+        (x0, x1), (y0, y1), (z0, z1) = s["own"]
+        (bx0, bx1), (by0, by1), (bz0, bz1) = s["box"]
+        rin = np.linalg.norm(yee.from_padded(rhs[:, bz0:bz1, by0:by1, bx0:bx1]))
+        d = out[:, z0:z1, y0:y1, x0:x1] - ref[:, z0:z1, y0:y1, x0:x1]
+        errs.append((idx, np.linalg.norm(d.ravel()) / max(rin, 1e-300)))
+    return errs
+
+
 @pytest.mark.parametrize("n,sub,blk,overlap", [
     (12, 4, 4, 1),                     # size class 8: boxes {5, 6}
     (21, 7, 3, 1),                     # odd sides {8, 9}: classes 8 and 16
@@ -154,10 +170,11 @@ def test_precond_reduced_precision_error_bound(precision, u, n, sub, blk, overla
     h.apply_precond(dev(P["rhs"]), z)
     ref = ras.ras_apply(P["rhs"], 2.0, P["sub"], overlap, eps_cell_of(P))
     out = host(z, ref.shape)
-    err = rel2(out, ref)
-    print(f"{precision} n={n} sub={sub} overlap={overlap}: 2-norm rel err {err:.3e} "
-          f"(bound {12 * u:.3e})")
-    assert err < 12 * u
+    errs = per_box_errors(out, ref, P["rhs"], P["sub"], overlap)
+    worst = max(errs, key=lambda e: e[1])
+    print(f"{precision} n={n} sub={sub} overlap={overlap}: worst box {worst[0]} error "
+          f"{worst[1]:.3e} (bound {12 * u:.3e}), whole vector {rel2(out, ref):.3e}")
+    assert worst[1] < 12 * u, worst
     assert np.all(out[~inputs.unknown_slots(n, n, n)] == 0.0)
 
 
@@ -175,6 +192,42 @@ def test_fgmres_with_reduced_precision_preconditioner(precision):
     res = np.linalg.norm(yee.from_padded(P["rhs"]) - A @ yee.from_padded(xs)) / np.linalg.norm(P["rhs"])
     assert res <= 1.5e-8
     assert info["iterations"] <= io["iterations"] + 3
+
+
+@pytest.mark.parametrize("solver,restart,per_it", [("bicgstab", 30, 2), ("fgmres", 30, 1),
+                                                    ("fgmres", 5, 1)])
+def test_table3_operation_counts(solver, restart, per_it):
+    """Table III: BiCGSTAB applies the preconditioner and the operator twice per
+    iteration, GMRES once each.  Besides those, the device solver applies the
+    operator for the initial residual and for the true residual recomputed at
+    BiCGSTAB's convergence check or at the end of every GMRES cycle.  The
+    oracle's drivers, with counting wrappers, do the same work (plus one last
+    operator apply for the residual they report)."""
+    import functools
+    P = problem(32, 16, 2.0, 8, seed=2)
+    _, Af, Mf = _oracle_ops(P)
+    calls = dict(A=0, M=0)
+
+    def Ac(v):
+        calls["A"] += 1
+        return Af(v)
+
+    def Mc(v):
+        calls["M"] += 1
+        return Mf(v)
+    run = krylov.bicgstab if solver == "bicgstab" else functools.partial(krylov.fgmres,
+                                                                         restart=restart)
+    _, io = run(Ac, P["rhs"], M=Mc, tol=1e-8, maxiter=300)
+    h = handle_for(P)
+    x = h.new_vector()
+    info = h.solve(dev(P["rhs"]), x, solver=solver, restart=restart, rtol=1e-8, max_iter=300)
+    it = info["iterations"]
+    assert info["status"] == "FMP_OK" and it >= 5
+    assert info["n_precond"] == per_it * it
+    extra = 2 if solver == "bicgstab" else 1 + -(-it // restart)
+    assert info["n_spmv"] == per_it * it + extra, info
+    if io["iterations"] == it:
+        assert calls["M"] == info["n_precond"] and calls["A"] - 1 == info["n_spmv"], (calls, info)
 
 
 def test_precond_batching_and_determinism():
@@ -463,9 +516,12 @@ def test_full_256_sampled_reduced_precision(precision, u):
     zo = host(z, P["rhs"].shape)
     which = [0, 7, 63, 511, 4 * 64 + 3 * 8 + 4]
     blocks = ras.ras_apply_subset(P["rhs"], P["c"], P["sub"], 1, eps_cell, which)
+    subs = ras.subdomains(256, 256, 256, P["sub"], 1)
     for idx, (own, blk) in blocks.items():
         (x0, x1), (y0, y1), (z0, z1) = own
-        err = rel2(zo[:, z0:z1, y0:y1, x0:x1], blk)
+        (bx0, bx1), (by0, by1), (bz0, bz1) = subs[idx]["box"]
+        rin = np.linalg.norm(yee.from_padded(P["rhs"][:, bz0:bz1, by0:by1, bx0:bx1]))
+        err = np.linalg.norm((zo[:, z0:z1, y0:y1, x0:x1] - blk).ravel()) / rin
         assert err < 12 * u, (idx, err)
 
 
