@@ -17,6 +17,10 @@ transforms Orthonormal DCT-II / DST-I matrices and the discrete transform
            exact_solve), restated for a PEC box.
 ras        Restricted additive Schwarz preconditioner built from exact box
            solves (Section II-B, the M_RAS^{-1} display).
+woodbury   The paper's index-block subdomain: compact differences and their
+           SVD (eq. (8)), exact_solve with that basis, the boundary term
+           Lambda = Q W Q^T / alpha and Algorithm 1's Woodbury correction
+           (Section III-A Step 4), and RAS over index blocks (overlap >= 0).
 krylov     Right-preconditioned BiCGSTAB and flexible GMRES(m) (Section IV-A
            workloads; Table III operation counts).
 coarse     Learned coarse correction reference: subdomain averaging R0,
