@@ -299,6 +299,34 @@ size_t fmp_mlp_scratch_bytes(int32_t in_dim, int32_t hidden, int32_t batch);
 fmp_status fmp_mlp_adam(int32_t n_params, float* params, const float* grads, float* m, float* v,
                         int32_t t, float lr, void* stream);
 
+/* ---- allocation-free variant (for callers that cannot allocate) -------------
+ * For callers that may not call hipMalloc or any allocating routine: code
+ * under hipGraph capture, tight training loops, harnesses that forbid device
+ * allocation.  fmp_mlp_loss_grad_noalloc computes exactly what
+ * fmp_mlp_loss_grad computes (same kernels, same order, bitwise the same
+ * loss and gradients) but takes its scratch (layer activations, hidden-layer
+ * gradients, loss partials) from a static device buffer of
+ * FMP_MLP_NOALLOC_SCRATCH_BYTES inside the library instead of a caller
+ * buffer.  It allocates nothing, host or device.
+ *   - Limit: fmp_mlp_scratch_bytes(in_dim, hidden, batch) must not exceed
+ *     FMP_MLP_NOALLOC_SCRATCH_BYTES (64 MiB; e.g. in_dim 1536, hidden 256,
+ *     batch <= 4095); larger shapes return FMP_ERR_WORKSPACE and
+ *     fmp_last_error(NULL) says by how much.
+ *   - The buffer of the GPU current on the calling thread is used (its
+ *     address is looked up once per GPU, on the first call with that GPU
+ *     current); `stream` must belong to that GPU.  Each GPU the library runs
+ *     on holds its own 64 MiB buffer until the process ends.
+ *   - Every call on one GPU shares that GPU's buffer: calls that overlap in
+ *     time on one GPU (different streams, or host threads, without ordering
+ *     between them) race on it and give undefined results.  Calls ordered on
+ *     one stream are safe.  No part of the buffer needs to start at zero.
+ *   - Other arguments, shapes and errors as fmp_mlp_loss_grad; FMP_ERR_HIP if
+ *     the buffer's device address cannot be obtained. */
+#define FMP_MLP_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+fmp_status fmp_mlp_loss_grad_noalloc(int32_t in_dim, int32_t hidden, int32_t batch,
+                                     const float* params, const float* X, const float* Y,
+                                     float* grads, float* loss_dev, void* stream);
+
 /* Release a handle.  Synchronises the device first (captured applies may
  * still replay on any stream), then frees the handle's graphs, private
  * streams, events and pinned host mirrors.  The caller's workspace is not
@@ -306,6 +334,8 @@ fmp_status fmp_mlp_adam(int32_t n_params, float* params, const float* grads, flo
  * is released either way). */
 fmp_status fmp_destroy(fmp_handle h);
 const char* fmp_status_string(fmp_status st);
+/* Detail message of the last error on handle h; with h == NULL, of the last
+ * failed call on this host thread that takes no handle. */
 const char* fmp_last_error(fmp_handle h);
 
 /* HIP versions in the HIP_VERSION encoding (major * 10^7 + minor * 10^5 +

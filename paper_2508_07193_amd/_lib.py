@@ -15,7 +15,8 @@ EXPORTS = ["fmp_setup_subdomains", "fmp_vector_layout", "fmp_curlcurl_apply", "f
            "fmp_autotune", "fmp_solve_workspace", "fmp_solve", "fmp_curl_e", "fmp_curl_h",
            "fmp_cn_workspace", "fmp_cn_step", "fmp_coarse_size", "fmp_set_coarse_model",
            "fmp_coarse_restrict", "fmp_mlp_loss_grad", "fmp_mlp_scratch_bytes", "fmp_mlp_adam",
-           "fmp_destroy", "fmp_status_string", "fmp_last_error", "fmp_runtime_version"]
+           "fmp_destroy", "fmp_status_string", "fmp_last_error", "fmp_runtime_version",
+           "fmp_mlp_loss_grad_noalloc"]
 
 
 class DomainDesc(C.Structure):
@@ -84,6 +85,7 @@ def load():
     L.fmp_mlp_scratch_bytes.argtypes = [i32, i32, i32]
     L.fmp_mlp_scratch_bytes.restype = sz
     L.fmp_mlp_adam.argtypes = [i32, vp, vp, vp, vp, i32, C.c_float, vp]
+    L.fmp_mlp_loss_grad_noalloc.argtypes = [i32, i32, i32, vp, vp, vp, vp, vp, vp]
     L.fmp_destroy.argtypes = [vp]
     L.fmp_status_string.argtypes = [i32]
     L.fmp_status_string.restype = C.c_char_p

@@ -272,3 +272,12 @@ def fmp_mlp_loss_grad(in_dim, hidden, batch, params, X, Y, grads, loss, scratch,
 def fmp_mlp_adam(params, grads, m, v, t, lr, stream=None):
     _check(_lib.load().fmp_mlp_adam(params.numel(), _ptr(params), _ptr(grads), _ptr(m), _ptr(v),
                                     int(t), float(lr), _stream(stream)), "fmp_mlp_adam")
+
+
+def fmp_mlp_loss_grad_noalloc(in_dim, hidden, batch, params, X, Y, grads, loss, stream=None):
+    """fmp_mlp_loss_grad with the library's static device scratch (allocates nothing)."""
+    L = _lib.load()
+    st = L.fmp_mlp_loss_grad_noalloc(in_dim, hidden, batch, _ptr(params), _ptr(X), _ptr(Y),
+                                     _ptr(grads), _ptr(loss), _stream(stream))
+    if st != 0:
+        raise FlashMPError(st, "fmp_mlp_loss_grad_noalloc", L.fmp_last_error(None).decode())

@@ -270,6 +270,10 @@ hipError_t fmp_coarse_resid_test(fmp_ctx* h, const double* v, const double* w, d
 size_t fmp_coarse_workspace(int nsub, int hidden_max);
 void fmp_coarse_bind(fmp_ctx* h, void* base);
 
+// Detail of the last failed call that has no handle, per host thread.
+static thread_local std::string g_free_err;
+void fmp::fmp_set_free_error(const std::string& msg) { g_free_err = msg; }
+
 extern "C" {
 
 const char* fmp_status_string(fmp_status st) {
@@ -286,7 +290,7 @@ const char* fmp_status_string(fmp_status st) {
   return "unknown status";
 }
 
-const char* fmp_last_error(fmp_handle h) { return h ? h->err.c_str() : "null handle"; }
+const char* fmp_last_error(fmp_handle h) { return h ? h->err.c_str() : g_free_err.c_str(); }
 
 fmp_status fmp_runtime_version(int32_t* compiled, int32_t* running) {
   if (!compiled || !running) return FMP_ERR_INVALID_ARG;

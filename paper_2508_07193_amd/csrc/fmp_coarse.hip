@@ -20,12 +20,20 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
 #include <vector>
 
 #include "fmp_common.h"
 #include "fmp_ctx.h"
 
 using namespace fmp;
+
+// Device scratch of fmp_mlp_loss_grad_noalloc: one copy per GPU, alive until
+// the process ends.  Host code never passes `scratch` itself to a kernel (on
+// the host it is a stand-in, not a device address): it takes the device
+// address hipGetSymbolAddress returns for the current GPU, once per GPU.
+static constexpr size_t kMlpStaticScratchBytes = FMP_MLP_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kMlpStaticScratchBytes];
 
 namespace {
 
@@ -515,11 +523,11 @@ size_t fmp_mlp_scratch_bytes(int32_t in, int32_t H, int32_t B) {
 }
 
 fmp_status fmp_mlp_loss_grad(int32_t in, int32_t H, int32_t B, const float* params, const float* X,
-                             const float* Y, float* grads, float* loss, void* scratch,
-                             size_t scratch_bytes, void* stream) {
-  if (in < 1 || H < 1 || B < 1 || !params || !X || !Y || !grads || !loss || !scratch)
+                             const float* Y, float* grads, float* loss, void* work,
+                             size_t work_bytes, void* stream) {
+  if (in < 1 || H < 1 || B < 1 || !params || !X || !Y || !grads || !loss || !work)
     return FMP_ERR_INVALID_ARG;
-  if (scratch_bytes < fmp_mlp_scratch_bytes(in, H, B)) return FMP_ERR_WORKSPACE;
+  if (work_bytes < fmp_mlp_scratch_bytes(in, H, B)) return FMP_ERR_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
   const float* W1 = params;
   const float* b1 = W1 + (size_t)H * in;
@@ -533,7 +541,7 @@ fmp_status fmp_mlp_loss_grad(int32_t in, int32_t H, int32_t B, const float* para
   float* gb2 = gW2 + (size_t)H * H;
   float* gW3 = gb2 + H;
   float* gb3 = gW3 + (size_t)in * H;
-  char* p = (char*)scratch;
+  char* p = (char*)work;
   auto take = [&](size_t bytes) { char* r = p; p += al(bytes); return (float*)r; };
   float* H1 = take((size_t)B * H * 4);
   float* H2 = take((size_t)B * H * 4);
@@ -568,6 +576,53 @@ fmp_status fmp_mlp_loss_grad(int32_t in, int32_t H, int32_t B, const float* para
     e = hipGetLastError();
   }
   return e == hipSuccess ? FMP_OK : FMP_ERR_HIP;
+}
+
+// Device address of `scratch` on the current GPU, looked up on the first call
+// made with that GPU current and kept per device ordinal.
+static constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_dev[kMaxDevices];
+
+static fmp_status static_scratch(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    fmp_set_free_error("fmp_mlp_loss_grad_noalloc: no current HIP device");
+    return FMP_ERR_HIP;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      fmp_set_free_error(std::string("fmp_mlp_loss_grad_noalloc: hipGetSymbolAddress: ") +
+                         hipGetErrorString(e));
+      return FMP_ERR_HIP;
+    }
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return FMP_OK;
+}
+
+fmp_status fmp_mlp_loss_grad_noalloc(int32_t in, int32_t H, int32_t B, const float* params,
+                                     const float* X, const float* Y, float* grads, float* loss,
+                                     void* stream) {
+  if (in < 1 || H < 1 || B < 1 || !params || !X || !Y || !grads || !loss)
+    return FMP_ERR_INVALID_ARG;
+  const size_t need = fmp_mlp_scratch_bytes(in, H, B);
+  if (need > kMlpStaticScratchBytes) {
+    fmp_set_free_error("fmp_mlp_loss_grad_noalloc: the shapes need " + std::to_string(need) +
+                       " bytes of scratch, more than the " +
+                       std::to_string(kMlpStaticScratchBytes) + " bytes of the static buffer");
+    return FMP_ERR_WORKSPACE;
+  }
+  void* p = nullptr;
+  const fmp_status st = static_scratch(&p);
+  if (st != FMP_OK) return st;
+  // every scratch region is written before it is read (layer outputs,
+  // gradients, per-block partials), so nothing needs clearing between calls
+  return fmp_mlp_loss_grad(in, H, B, params, X, Y, grads, loss, p, kMlpStaticScratchBytes, stream);
 }
 
 fmp_status fmp_mlp_adam(int32_t n, float* params, const float* grads, float* m, float* v, int32_t t,

@@ -178,6 +178,10 @@ hipError_t launch_bicg_xr(double* x, const double* phat, const double* shat, con
                           const double* t, double* r, const double* rhat, const double* S,
                           long long len, double* partials, hipStream_t s);
 
+// Records the detail message that fmp_last_error(NULL) returns on this host
+// thread (calls that take no handle).
+void fmp_set_free_error(const std::string& msg);
+
 // ---- learned coarse correction ---------------------------------------------
 hipError_t launch_coarse_restrict(const double* r, const BoxDev* boxes, int nbox,
                                   const DomainDev* doms, double* rc, hipStream_t s);
