@@ -90,13 +90,26 @@ typedef struct {
  * use_graph: 1 = the launch sequence of an apply is captured once per
  *   (r, z) pair into a hipGraph (on a private stream, default priority) and
  *   replayed on the caller's stream; at most 64 pairs are cached, further
- *   pairs run uncaptured.  Results are identical to uncaptured applies. */
+ *   pairs run uncaptured.  Results are identical to uncaptured applies.
+ * subdomain: the subdomain of each Schwarz term.
+ *   0 = PEC box (default): the unknowns strictly inside the owned block
+ *       extended by `overlap` cells (overlap >= 1), one exact transform solve
+ *       per box (Sec. III-A Steps 1-3).
+ *   1 = index block (Sec. III-A Step 4; Algorithm 1 main body): the unknowns
+ *       whose half-point and node indices lie in [a - overlap, a + n + overlap)
+ *       along every axis, clipped at the grid (overlap >= 0).  Each apply
+ *       runs two exact solves with the compact-difference bases around the
+ *       low-rank boundary correction C^{-1} (one dense (6n^2-3n)^2 matrix per
+ *       distinct box shape, wall pattern and alpha, built on the device at
+ *       setup; 293 MB at n = 32).  FP64 only, sides <= 48, no learned part,
+ *       no autotuner (FMP_ERR_UNSUPPORTED otherwise). */
 typedef struct {
   int32_t overlap;
   int32_t precision;
   int32_t use_learned;
   int32_t batch_boxes;
   int32_t use_graph;
+  int32_t subdomain;
 } fmp_precond_desc;
 
 /* Krylov options.  solver: 0 = BiCGSTAB, 1 = flexible GMRES(restart).

@@ -9,6 +9,7 @@ STATUS = {0: "FMP_OK", 1: "FMP_NOT_CONVERGED", -1: "FMP_ERR_INVALID_ARG", -2: "F
           -3: "FMP_ERR_WORKSPACE", -4: "FMP_ERR_HIP", -5: "FMP_ERR_BREAKDOWN",
           -6: "FMP_ERR_UNSUPPORTED"}
 PRECISION = {"fp64": 0, "fp32": 1, "bf16": 2}
+SUBDOMAIN = {"pec": 0, "index": 1}
 
 # every symbol include/flashmp.h declares
 EXPORTS = ["fmp_setup_subdomains", "fmp_vector_layout", "fmp_curlcurl_apply", "fmp_apply_precond",
@@ -27,7 +28,7 @@ class DomainDesc(C.Structure):
 
 class PrecondDesc(C.Structure):
     _fields_ = [("overlap", C.c_int32), ("precision", C.c_int32), ("use_learned", C.c_int32),
-                ("batch_boxes", C.c_int32), ("use_graph", C.c_int32)]
+                ("batch_boxes", C.c_int32), ("use_graph", C.c_int32), ("subdomain", C.c_int32)]
 
 
 class TuneEntry(C.Structure):

@@ -64,7 +64,7 @@ class Handle:
     """A set of domains with their RAS plans (fmp_setup_subdomains) and workspace."""
 
     def __init__(self, domains, overlap=1, precision="fp64", use_learned=False, batch_boxes=0,
-                 use_graph=False, device="cuda", stream=None):
+                 use_graph=False, device="cuda", stream=None, subdomain="pec"):
         L = _lib.load()
         keep = []
         arr = (_lib.DomainDesc * len(domains))()
@@ -73,7 +73,7 @@ class Handle:
             arr[i] = d
             keep.append(k)
         pd = _lib.PrecondDesc(int(overlap), _lib.PRECISION[precision], int(bool(use_learned)),
-                              int(batch_boxes), int(bool(use_graph)))
+                              int(batch_boxes), int(bool(use_graph)), _lib.SUBDOMAIN[subdomain])
         nbytes = C.c_size_t(0)
         h = C.c_void_p()
         s = _stream(stream)

@@ -205,6 +205,7 @@ static fmp_status precond_apply(fmp_ctx* h, const double* r, double* z, hipStrea
 
 static fmp_status precond_launches(fmp_ctx* h, const double* r, double* z, hipStream_t s,
                                    const double* coarse) {
+  if (h->ib.on) return ib_apply(h, r, z, s);
   const int prec = h->prec;
   // Several batches: batch k runs on private stream k % ns with staging
   // buffer k % ns, so the passes of up to ns batches overlap.  Batches write
@@ -305,8 +306,15 @@ fmp_status fmp_setup_subdomains(const fmp_domain_desc* domains, int32_t n_domain
                                 const fmp_precond_desc* pd, void* ws, size_t* ws_bytes,
                                 void* stream, fmp_handle* out) {
   if (!domains || n_domains < 1 || !pd || !ws_bytes) return FMP_ERR_INVALID_ARG;
-  if (pd->overlap < 1) return FMP_ERR_INVALID_ARG;
+  if (pd->subdomain != 0 && pd->subdomain != 1) return FMP_ERR_INVALID_ARG;
+  const bool index_blocks = pd->subdomain == 1;
+  // PEC boxes need an overlap of at least one cell: with none, the owned
+  // interface unknowns would sit on box walls and never be corrected
+  if (pd->overlap < (index_blocks ? 0 : 1)) return FMP_ERR_INVALID_ARG;
   if (pd->precision < FMP_FP64 || pd->precision > FMP_BF16) return FMP_ERR_INVALID_ARG;
+  // the index-block path is FP64, without the learned part or the autotuner
+  if (index_blocks && (pd->precision != FMP_FP64 || pd->use_learned || pd->batch_boxes < 0))
+    return FMP_ERR_UNSUPPORTED;
   if (out) *out = nullptr;
   std::unique_ptr<fmp_ctx> h(new fmp_ctx());
   h->prec = pd->precision;
@@ -392,6 +400,11 @@ fmp_status fmp_setup_subdomains(const fmp_domain_desc* domains, int32_t n_domain
   }
   h->offsets.push_back(off);
   h->len = off;
+  if (index_blocks && h->precond_ok) {
+    const fmp_status st = ib_prepare(h.get());
+    if (st != FMP_OK) return st;
+    std::fill(sides_used.begin(), sides_used.end(), 0);   // no PEC-box tables
+  }
   if (n_domains > kRedBlocks) {
     h->err = "more domains than reduction blocks (1024)";
     return FMP_ERR_UNSUPPORTED;
@@ -559,6 +572,8 @@ fmp_status fmp_setup_subdomains(const fmp_domain_desc* domains, int32_t n_domain
   const size_t o_SD = cur; cur = align_up(cur + sd_bytes);
   const size_t o_learn = cur;
   if (h->use_learned) cur = align_up(cur + fmp_coarse_workspace(h->nsub, 512));
+  const size_t o_ib = cur;
+  if (h->ib.on) cur = align_up(cur + ib_workspace_bytes(h.get()));
   // staging buffers: one per batch stream (a tunable handle keeps room for
   // the most streams fmp_autotune tries)
   h->n_wbuf = h->tunable ? fmp_ctx::kMaxStreams : (h->launches.size() > 1 ? 2 : 1);
@@ -646,6 +661,10 @@ fmp_status fmp_setup_subdomains(const fmp_domain_desc* domains, int32_t n_domain
   h->h_fac = h->h_SD + (size_t)n_domains * kSD;
   h->h_act = (int*)(h->h_fac + n_domains);
   HIPCHK(hp, hipStreamSynchronize(s));   // host staging vectors go out of scope
+  if (h->ib.on) {
+    const fmp_status st = ib_bind(hp, base + o_ib, s);
+    if (st != FMP_OK) return st;
+  }
   *out = h.release();
   return FMP_OK;
 }

@@ -57,6 +57,27 @@ struct BoxDev {
   double alpha;         // c / mean eps over the owned block
   int wzp;              // MFMA staging: nz rounded up to 4 (chunks of 4 z values)
   int pad_;
+  // index-block subdomains (low-rank boundary correction) only:
+  int ibt[3];           // per axis: offset of the side's compact-difference tables
+  int wall;             // bit a: the box starts at the PEC wall along axis a
+  int corr;             // correction matrix of the box
+  int m;                // boundary slots (columns of Q)
+  int qoff;             // offset of the box shape's boundary slot list
+  int pad2_;
+  long long g_off;      // offset of the box's boundary vectors Q^T E, C^{-1} Q^T E
+};
+
+// Index-block tables, per distinct side n (row stride kIT, zero padded):
+// [0] forward along the half-point axis (U^T), [1] its inverse (U),
+// [2] forward along a node axis (V^T), [3] its inverse (V), [4] sigma.
+constexpr int kIT = 48;
+constexpr int kIBMaxSide = 48;
+constexpr long long kIBPerSide = 4LL * kIT * kIT + kIT;
+
+// One correction matrix C^{-1} (mp x mp, row-major, padded with the identity).
+struct IBCorrDev {
+  long long off;
+  int m, mp;
 };
 
 // Staging elements of one component of a box: dense [z][y][x] for the
@@ -177,6 +198,23 @@ hipError_t launch_bicg_s(const double* r, const double* v, double* sv, const dou
 hipError_t launch_bicg_xr(double* x, const double* phat, const double* shat, const double* sv,
                           const double* t, double* r, const double* rhat, const double* S,
                           long long len, double* partials, hipStream_t s);
+
+// ---- index-block subdomains with the low-rank boundary correction ----------
+// Exact solve (I + alpha M)^{-1} per box: three passes like the PEC boxes but
+// with dense compact-difference bases.  Pass A reads r (gather, wall slots 0)
+// or, with Win set, staged box arrays; pass C writes the full box arrays to
+// Wdst, or, with z set, z = E - (its result) on the owned unknowns.
+int ib_class_np(int cls);
+int ib_class_of(int n);
+int ib_zslab(int np);
+hipError_t launch_ib_a(int np, const double* r, const double* Win, double* W, const BoxDev* boxes,
+                       const DomainDev* doms, const int4* work, int nwork, const double* tab,
+                       hipStream_t s);
+hipError_t launch_ib_b(int np, double* W, const BoxDev* boxes, const int4* work, int nwork,
+                       const double* tab, hipStream_t s);
+hipError_t launch_ib_c(int np, const double* Wsrc, double* Wdst, const double* E, double* z,
+                       const BoxDev* boxes, const DomainDev* doms, const int4* work, int nwork,
+                       const double* tab, hipStream_t s);
 
 // Records the detail message that fmp_last_error(NULL) returns on this host
 // thread (calls that take no handle).

@@ -9,11 +9,65 @@
 using fmp::BoxDev;
 using fmp::DomainDev;
 using fmp::StencilTile;
+using fmp::IBCorrDev;
 
 struct Launch {
   int cls;
   int a0, na;   // pass A / C work items
   int b0, nb;   // pass B work items
+};
+
+// Index-block subdomains with Algorithm 1's low-rank boundary correction.
+struct IBCorr {
+  int nx, ny, nz, wall;   // box shape and low-wall bits
+  double alpha;
+  int m, mp;              // boundary slots; padded order (multiple of 64)
+  int qoff;               // boundary slot list of the shape
+  long long off;          // offset (doubles) of C^{-1}
+  int rep;                // one box that uses it
+};
+
+struct IBPlan {
+  bool on = false;
+  std::vector<BoxDev> boxes;
+  std::vector<double> tab;
+  std::vector<int> qidx;
+  std::vector<IBCorr> corr;
+  struct Cls {
+    int np, a0, na, b0, nb;
+  };
+  std::vector<Cls> cls;
+  std::vector<int4> work_a, work_b;
+  std::vector<int4> gemv;      // (correction, first row, first gbox entry, boxes)
+  std::vector<int> gbox;       // boxes grouped by correction matrix
+  long long w_elems = 0;       // staging of all boxes (one buffer)
+  long long g_elems = 0;
+  long long cinv_elems = 0;
+  long long stage_elems = 0;   // W_E + W_C region (also the unit-solve staging at setup)
+  int unit_batch = 0;
+  int m_max = 0, mp_max = 0;
+  long long vol_max = 0;
+  BoxDev* d_boxes = nullptr;
+  double* d_tab = nullptr;
+  int* d_qidx = nullptr;
+  IBCorrDev* d_corr = nullptr;
+  int4* d_work_a = nullptr;
+  int4* d_work_b = nullptr;
+  int4* d_gemv = nullptr;
+  int* d_gbox = nullptr;
+  double* d_WE = nullptr;
+  double* d_WC = nullptr;
+  double* d_g = nullptr;
+  double* d_hv = nullptr;
+  double* d_cinv = nullptr;
+  // setup only: pivot block, row and column panels, W^{-1}, unit-box records
+  double* d_P = nullptr;
+  double* d_Row = nullptr;
+  double* d_Col = nullptr;
+  double* d_winv = nullptr;
+  BoxDev* d_ubox = nullptr;
+  int4* d_uwork_a = nullptr;
+  int4* d_uwork_b = nullptr;
 };
 
 struct fmp_ctx {
@@ -97,6 +151,13 @@ struct fmp_ctx {
   hipEvent_t ev_fork = nullptr;
   hipEvent_t ev_join[kMaxStreams] = {nullptr, nullptr};
   std::vector<Graph> graphs;
+  IBPlan ib;
   std::string err;
 };
+
+// index-block subdomains (fmp_woodbury.hip)
+fmp_status ib_prepare(fmp_ctx* h);                       // plans, tables, slot lists
+size_t ib_workspace_bytes(const fmp_ctx* h);
+fmp_status ib_bind(fmp_ctx* h, char* base, hipStream_t s);   // upload, build C^{-1}
+fmp_status ib_apply(fmp_ctx* h, const double* r, double* z, hipStream_t s);
 

@@ -78,3 +78,29 @@ def test_oversized_boxes_still_get_a_workspace_size(L):
 def test_status_strings(L):
     assert L.fmp_status_string(0) == b"ok"
     assert L.fmp_status_string(-2) == b"input and output overlap"
+
+
+def _size_pd(L, descs, pd):
+    arr = (_lib.DomainDesc * len(descs))(*descs)
+    nb = C.c_size_t(0)
+    h = C.c_void_p()
+    st = L.fmp_setup_subdomains(arr, len(descs), C.byref(pd), None, C.byref(nb), None, C.byref(h))
+    return st, nb.value
+
+
+def test_index_block_workspace_query(L):
+    # 64^3 in 32^3 index blocks, overlap 0: eight wall patterns, eight C^{-1}
+    # of order 6n^2 - 3n = 6048 (padded to 6080), Table II's dense matrix each
+    st, nb = _size_pd(L, [_desc(64, 32)], _lib.PrecondDesc(0, 0, 0, 0, 0, 1))
+    assert st == 0
+    assert nb >= 8 * 6080 * 6080 * 8
+    # overlap 0 is admissible for index blocks only
+    st, _ = _size_pd(L, [_desc(64, 32)], _lib.PrecondDesc(0, 0, 0, 0, 0, 0))
+    assert st == -1
+    # FP32 transforms, the learned part and the autotuner are PEC-box features
+    for pd in (_lib.PrecondDesc(0, 1, 0, 0, 0, 1), _lib.PrecondDesc(0, 0, 1, 0, 0, 1),
+               _lib.PrecondDesc(0, 0, 0, -1, 0, 1)):
+        st, _ = _size_pd(L, [_desc(64, 32)], pd)
+        assert st == -6
+    st, _ = _size_pd(L, [_desc(64, 32)], _lib.PrecondDesc(0, 0, 0, 0, 0, 2))
+    assert st == -1
