@@ -374,23 +374,48 @@ def batch_leg(args, dev, log):
 def convergence_leg(args, dev, log):
     """Shape of the overlap study of Sec. IV (convergence experiments): uniform
     medium, b = A x_rand, stopping at relative residual 1e-12; no
-    preconditioner versus RAS with overlap 1, 2, 3, each under BiCGSTAB and
-    FGMRES(30).  128^3 grid, 4^3 subdomains of 32^3, c = 2, FP64 transforms.
-    (Overlap 0 is not admissible with PEC-box subdomains: the interface
-    unknowns would sit on box walls and never be corrected.)"""
+    preconditioner versus RAS with overlap 1, 2, 3 (PEC boxes), and RAS over
+    the paper's index blocks with the low-rank boundary correction at overlap
+    0 and 1, each under BiCGSTAB and FGMRES(30).  128^3 grid, 4^3 subdomains
+    of 32^3, c = 2, FP64 transforms.  (Overlap 0 exists for index blocks
+    only: with PEC boxes the interface unknowns would sit on box walls.)"""
     import torch
     from paper_2508_07193_amd import api, inputs
     n, sub, c = 128, 32, 2.0
     xr = torch.from_numpy(inputs.normal_rhs(np.random.default_rng(11), n, n, n).ravel()).to(dev)
     dom = [dict(nx=n, ny=n, nz=n, c=c, sub=(sub, sub, sub))]
     rows = []
-    for g in (0, 1, 2, 3):
-        h = api.Handle(dom, overlap=max(g, 1), precision="fp64", device=dev)
+    index_setup = {}
+    cases = [("pec", g) for g in (0, 1, 2, 3)] + [("index", 0), ("index", 1)]
+    for kind, g in cases:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = api.Handle(dom, overlap=g if kind == "index" else max(g, 1), precision="fp64",
+                       device=dev, subdomain=kind)
+        torch.cuda.synchronize()
+        if kind == "index":
+            r = xr.clone()
+            z = h.new_vector()
+            h.apply_precond(r, z)
+            torch.cuda.synchronize()
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ev0.record()
+            for _ in range(5):
+                h.apply_precond(r, z)
+            ev1.record()
+            torch.cuda.synchronize()
+            index_setup[f"overlap{g}"] = dict(
+                setup_ms=round((time.perf_counter() - t0) * 1e3, 1),
+                apply_ms=round(ev0.elapsed_time(ev1) / 5, 3),
+                workspace_gb=round(h.ws.numel() / 1e9, 2))
+            log(f"[convergence] index blocks overlap {g}: {index_setup[f'overlap{g}']}")
+            del r, z
         b = h.new_vector()
         h.curlcurl_apply(xr, b)
         x = h.new_vector()
         for solver in ("bicgstab", "fgmres"):
-            kw = dict(solver=solver, rtol=1e-12, max_iter=3000, precond=g > 0)
+            precond = kind == "index" or g > 0
+            kw = dict(solver=solver, rtol=1e-12, max_iter=3000, precond=precond)
             x.zero_()
             h.solve(b, x, **kw)
             x.zero_()
@@ -400,15 +425,19 @@ def convergence_leg(args, dev, log):
             torch.cuda.synchronize()
             tts = (time.perf_counter() - t0) * 1e3
             err = float(torch.linalg.vector_norm(x - xr) / torch.linalg.vector_norm(xr))
-            rows.append(dict(precond=f"ras_overlap{g}" if g else "none", solver=solver,
+            name = (f"ras_index_overlap{g}" if kind == "index" else
+                    (f"ras_overlap{g}" if g else "none"))
+            rows.append(dict(precond=name, solver=solver,
                              iterations=info["iterations"], time_to_solution_ms=round(tts, 2),
                              rel_residual_true=info["rel_residual_true"], rel_err_vs_x_rand=err,
                              status=info["status"]))
             log(f"[convergence] {rows[-1]}")
         h.close()
+        del h, b, x
+        torch.cuda.empty_cache()
     return dict(workload="128^3 Yee grid, PEC walls, eps 1, c=2, 4^3 subdomains of 32^3, "
                          "b = A x_rand (x_rand N(0,1) seed 11), rel. residual 1e-12",
-                rows=rows)
+                rows=rows, index_blocks=index_setup)
 
 
 def cn_leg(args, dev, log):
@@ -464,15 +493,16 @@ def cn_leg(args, dev, log):
 
 def whole_leg(args, dev, log):
     """The 64 uneven domains of the batch leg solved with one box per domain
-    (sides up to 96: the matrix-core size classes 64 and 96) and BF16
-    transforms: the preconditioner is each domain's exact inverse up to bf16
-    rounding.  Independent FGMRES(30) per domain in FP64 to 1e-8, lockstep,
-    hipGraph replay of the applies."""
+    (sides up to 96: the size classes 64 and 96, as matrix-core GEMMs in BF16
+    or tiled vector-ALU GEMMs in FP32): the preconditioner is each domain's
+    exact inverse up to the transform rounding.  Independent FGMRES(30) per
+    domain in FP64 to 1e-8, lockstep, hipGraph replay of the applies."""
     import torch
     from paper_2508_07193_amd import api, inputs
+    prec = args.prec or "bf16"
     doms_in = inputs.make_batch_c4()
     doms = [dict(nx=d["nx"], ny=d["ny"], nz=d["nz"], c=d["c"], sub=(0, 0, 0)) for d in doms_in]
-    h = api.Handle(doms, overlap=1, precision="bf16", device=dev, use_graph=True, batch_boxes=-1)
+    h = api.Handle(doms, overlap=1, precision=prec, device=dev, use_graph=True, batch_boxes=-1)
     b = torch.cat([torch.from_numpy(d["rhs"].ravel()) for d in doms_in]).to(dev)
     z = h.new_vector()
     tune = h.autotune(b, z)
@@ -497,12 +527,13 @@ def whole_leg(args, dev, log):
         a, e = h.offsets[d], h.offsets[d + 1]
         rel.append(float(torch.linalg.vector_norm(b[a:e] - y[a:e]) / torch.linalg.vector_norm(b[a:e])))
     its = sorted(info["domain_iterations"])
-    log(f"[whole] lockstep {info['iterations']}, per-domain {its}, tts {tts:.1f} ms, "
+    log(f"[whole {prec}] lockstep {info['iterations']}, per-domain {its}, tts {tts:.1f} ms, "
         f"max domain rel res {max(rel):.2e}, precond {t_pre:.3f} ms")
     chosen = [t for t in tune if t["chosen"]][0]
-    return dict(workload="the 64 domains of batch_c4, one box per domain (sides 24..96), BF16 "
-                         "transforms on the matrix cores; independent FGMRES(30) per domain, FP64, "
-                         "to 1e-8 each",
+    kind = ("BF16 transforms on the matrix cores" if prec == "bf16" else
+            f"{prec.upper()} transforms (tiled GEMMs for sides above 48)")
+    return dict(workload=f"the 64 domains of batch_c4, one box per domain (sides 24..96), {kind}; "
+                         "independent FGMRES(30) per domain, FP64, to 1e-8 each",
                 time_to_solution_ms=round(tts, 2), lockstep_steps=info["iterations"],
                 domain_steps_min_median_max=[its[0], its[len(its) // 2], its[-1]],
                 max_domain_rel_residual=max(rel), precond_ms=round(t_pre, 4),
@@ -786,6 +817,7 @@ def main():
         if args.batch:
             out["variants"]["batch_c4"] = child(args, "batch")
             out["variants"]["batch_c4_whole_domain_bf16"] = child(args, "whole")
+            out["variants"]["batch_c4_whole_domain_fp32"] = child(args, "whole", ["--prec", "fp32"])
         if args.learned:
             out["variants"]["learned_c5"] = child(args, "learned")
         if args.convergence:

@@ -178,10 +178,12 @@ typedef struct {
  * at least *ws_bytes bytes (256-byte aligned) to get a handle in *out.
  * Errors: FMP_ERR_INVALID_ARG (sizes < 2, overlap < 1, sub not dividing the
  * side, eps table missing its block size), FMP_ERR_WORKSPACE.  A domain
- * whose boxes exceed the largest compiled transform size (48 cells with FP64
- * or FP32 transforms, 96 cells with BF16 transforms on the matrix cores)
- * still gets a handle: the stencil and unpreconditioned solves work, while
- * fmp_apply_precond and preconditioned solves return FMP_ERR_UNSUPPORTED. */
+ * whose boxes exceed the largest compiled transform size (96 cells for PEC
+ * boxes in every precision: up to 48 with the butterfly passes, 49..96 with
+ * the contractions as tiled GEMMs (FP64 / FP32) or matrix-core GEMMs (BF16);
+ * 48 cells for index blocks) still gets a handle: the stencil and
+ * unpreconditioned solves work, while fmp_apply_precond and preconditioned
+ * solves return FMP_ERR_UNSUPPORTED. */
 fmp_status fmp_setup_subdomains(const fmp_domain_desc* domains, int32_t n_domains,
                                 const fmp_precond_desc* pd, void* ws, size_t* ws_bytes,
                                 void* stream, fmp_handle* out);

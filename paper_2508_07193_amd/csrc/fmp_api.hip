@@ -71,9 +71,16 @@ int class_of(int n) {
 // partial lines at both ends of every 34-cell row) are fetched once into the
 // XCD's L2, at the price of more distinct pages in flight.  Returns the
 // largest batch's staging size (elements).
+// FP64 / FP32 boxes of the classes above the vector-ALU passes' limit run the
+// tiled-GEMM path, whose staging keeps two copies of each box.
+bool large_class(const fmp_ctx* h, int c) {
+  return c >= 0 && h->prec != FMP_BF16 && kClasses[c] > kMaxSideVec;
+}
+
 long long plan_batches(fmp_ctx* h, int batch) {
   h->launches.clear();
   h->work_a.clear();
+  h->work_l.clear();
   h->batch = batch;
   long long wmax = 0;
   const auto cls_at = [&](size_t i) {
@@ -89,7 +96,8 @@ long long plan_batches(fmp_ctx* h, int batch) {
     for (size_t i = i0; i < i1; ++i) {
       BoxDev& B = h->boxes[h->order[i]];
       B.w_off = woff;                 // staging is reused batch after batch
-      woff += (3 * box_wvol(B, h->prec == FMP_BF16) + 7) / 8 * 8;   // 16-byte aligned boxes
+      woff += (large_class(h, c) ? 2 : 1) *
+              ((3 * box_wvol(B, h->prec == FMP_BF16) + 7) / 8 * 8);   // 16-byte aligned boxes
       nzmax = std::max(nzmax, B.nz);
     }
     wmax = std::max(wmax, woff);
@@ -108,8 +116,25 @@ long long plan_batches(fmp_ctx* h, int batch) {
             for (int z0 = 0; z0 < h->boxes[h->order[i]].nz; z0 += zs)
               h->work_a.push_back(make_int4(h->order[i], q, z0, 0));
       }
-      h->launches.push_back(Launch{c, a0, (int)h->work_a.size() - a0, h->wb0[i0],
-                                   h->wb0[i1] - h->wb0[i0]});
+      Launch L{c, a0, (int)h->work_a.size() - a0, h->wb0[i0], h->wb0[i1] - h->wb0[i0],
+               {0, 0, 0}, {0, 0, 0}};
+      if (large_class(h, c)) {
+        const int TI = large_tile_rows(), TC = large_tile_cols();
+        for (int a = 0; a < 3; ++a) {
+          L.l0[a] = (int)h->work_l.size();
+          for (size_t i = i0; i < i1; ++i) {
+            const BoxDev& B = h->boxes[h->order[i]];
+            const int n = a == 0 ? B.nx : (a == 1 ? B.ny : B.nz);
+            const long long ncol = B.vol / n;
+            for (int q = 0; q < 3; ++q)
+              for (int it = 0; it * TI < n; ++it)
+                for (long long ct = 0; ct * TC < ncol; ++ct)
+                  h->work_l.push_back(make_int4(h->order[i], q, it, (int)ct));
+          }
+          L.nl[a] = (int)h->work_l.size() - L.l0[a];
+        }
+      }
+      h->launches.push_back(L);
     }
     i0 = i1;
   }
@@ -232,7 +257,11 @@ static fmp_status precond_launches(fmp_ctx* h, const double* r, double* z, hipSt
     const int slot = ns > 1 ? (int)(k % ns) : 0;
     const hipStream_t st = bs[slot];
     void* W = h->d_Wk[slot];
-    if (prec == FMP_BF16) {
+    if (large_class(h, L.cls)) {
+      HIPCHK(h, launch_large(prec, r, W, z, h->d_boxes, h->d_doms, h->d_work_a + L.a0, L.na,
+                             h->d_work_l, L.l0, L.nl, pass_a_zslab(L.cls), h->d_tab, coarse,
+                             h->nsub, st));
+    } else if (prec == FMP_BF16) {
       HIPCHK(h, launch_mfma_pass_a(L.cls, r, W, h->d_boxes, h->d_doms,
                                    h->d_work_a + L.a0, L.na, (const __hip_bfloat16*)h->d_tab, st));
       HIPCHK(h, launch_mfma_pass_b(L.cls, W, h->d_boxes, h->d_work_b + L.b0, L.nb,
@@ -378,7 +407,7 @@ fmp_status fmp_setup_subdomains(const fmp_domain_desc* domains, int32_t n_domain
           B.wzp = (B.nz + 3) / 4 * 4;
           if (std::min(B.nx, std::min(B.ny, B.nz)) < 2) return FMP_ERR_INVALID_ARG;
           const int side_max = std::max(B.nx, std::max(B.ny, B.nz));
-          if (side_max > kMaxSide || (side_max > kMaxSideVec && h->prec != FMP_BF16))
+          if (side_max > kMaxSide || (index_blocks && side_max > kIBMaxSide))
             h->precond_ok = false;
           else
             sides_used[B.nx] = sides_used[B.ny] = sides_used[B.nz] = 1;
@@ -565,6 +594,7 @@ fmp_status fmp_setup_subdomains(const fmp_domain_desc* domains, int32_t n_domain
   const size_t o_sig32 = cur; cur = align_up(cur + std::max<size_t>(tab64.size() * 4, 1));
   const size_t o_wa = cur; cur = align_up(cur + std::max<size_t>(h->work_a.size(), 1) * sizeof(int4));
   const size_t o_wb = cur; cur = align_up(cur + work_b.size() * sizeof(int4));
+  const size_t o_wl = cur; cur = align_up(cur + std::max<size_t>(h->work_l.size(), 1) * sizeof(int4));
   const size_t o_part = cur; cur = align_up(cur + (size_t)kMaxDots * kRedBlocks * 8);
   const size_t o_S = cur; cur = align_up(cur + kScal * 8);
   const size_t o_map = cur; cur = align_up(cur + (2 * (size_t)kRedBlocks + 1 + n_domains) * sizeof(SegDev));
@@ -607,6 +637,7 @@ fmp_status fmp_setup_subdomains(const fmp_domain_desc* domains, int32_t n_domain
   h->d_sig32 = (float*)(base + o_sig32);
   h->d_work_a = (int4*)(base + o_wa);
   h->d_work_b = (int4*)(base + o_wb);
+  h->d_work_l = (int4*)(base + o_wl);
   h->d_part = (double*)(base + o_part);
   h->d_S = (double*)(base + o_S);
   h->d_map_glob = (SegDev*)(base + o_map);
@@ -648,6 +679,9 @@ fmp_status fmp_setup_subdomains(const fmp_domain_desc* domains, int32_t n_domain
                             hipMemcpyHostToDevice, s));
   HIPCHK(hp, hipMemcpyAsync(h->d_work_b, work_b.data(), work_b.size() * sizeof(int4),
                             hipMemcpyHostToDevice, s));
+  if (!h->work_l.empty())
+    HIPCHK(hp, hipMemcpyAsync(h->d_work_l, h->work_l.data(), h->work_l.size() * sizeof(int4),
+                              hipMemcpyHostToDevice, s));
   HIPCHK(hp, hipMemcpyAsync(h->d_map_glob, map_glob.data(), kRedBlocks * sizeof(SegDev),
                             hipMemcpyHostToDevice, s));
   HIPCHK(hp, hipMemcpyAsync(h->d_map_dom, map_dom.data(), kRedBlocks * sizeof(SegDev),
@@ -756,6 +790,9 @@ fmp_status fmp_autotune(fmp_handle h, const double* r, double* z, fmp_tune_entry
                              hipMemcpyHostToDevice, s));
     HIPCHK(h, hipMemcpyAsync(h->d_work_a, h->work_a.data(), h->work_a.size() * sizeof(int4),
                              hipMemcpyHostToDevice, s));
+    if (!h->work_l.empty())
+      HIPCHK(h, hipMemcpyAsync(h->d_work_l, h->work_l.data(), h->work_l.size() * sizeof(int4),
+                               hipMemcpyHostToDevice, s));
     HIPCHK(h, hipStreamSynchronize(s));
     return FMP_OK;
   };

@@ -136,6 +136,17 @@ hipError_t launch_pass_c(int prec, int cls, const void* W, double* z, const BoxD
                          const double* coarse, int nsub, hipStream_t s);
 int pass_a_zslab(int cls);   // planes per pass-A/C work item for a class
 
+// FP64 / FP32 boxes of the classes above kMaxSideVec: gather, three forward
+// and three inverse contractions as tiled GEMMs (items work_l + l0[a], nl[a]
+// per axis a: box, component, row tile, column tile), solve, scatter; the
+// staging holds two copies of each box.
+int large_tile_rows();
+int large_tile_cols();
+hipError_t launch_large(int prec, const double* r, void* W, double* z, const BoxDev* boxes,
+                        const DomainDev* doms, const int4* work_a, int na, const int4* work_l,
+                        const int* l0, const int* nl, int zs, const void* tab,
+                        const double* coarse, int nsub, hipStream_t s);
+
 // BF16 MFMA transform passes (staging W in bf16).
 hipError_t launch_mfma_pass_a(int cls, const double* r, void* W, const BoxDev* boxes,
                               const DomainDev* doms, const int4* work, int nwork,

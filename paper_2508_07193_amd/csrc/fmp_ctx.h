@@ -15,6 +15,7 @@ struct Launch {
   int cls;
   int a0, na;   // pass A / C work items
   int b0, nb;   // pass B work items
+  int l0[3], nl[3];   // large classes (FP64 / FP32): contraction items per axis
 };
 
 // Index-block subdomains with Algorithm 1's low-rank boundary correction.
@@ -80,6 +81,7 @@ struct fmp_ctx {
   // (elements) and the current plan's knobs
   std::vector<int> order, wb0;
   std::vector<int4> work_a;    // pass A / C items of the current plan (see plan_batches)
+  std::vector<int4> work_l;    // contraction items of large FP64 / FP32 boxes
   long long w_cap = 0;
   int batch = 0;               // boxes per batch
   int nstreams = 2;            // 1 = batches in order on the caller's stream
@@ -100,6 +102,7 @@ struct fmp_ctx {
   float* d_sig32 = nullptr;
   int4* d_work_a = nullptr;
   int4* d_work_b = nullptr;
+  int4* d_work_l = nullptr;
   void* d_W = nullptr;
   double* d_part = nullptr;
   double* d_S = nullptr;

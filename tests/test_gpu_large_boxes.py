@@ -1,12 +1,18 @@
-"""Boxes of 49..96 cells: the size classes 64 and 96, which exist on the
-matrix-core (BF16) transform path only.  Whole-domain boxes (one PEC box
-covering a 64³ or 96³ domain) make the preconditioner the exact inverse up to
-bf16 rounding, so FGMRES converges in a few steps.
+"""Boxes of 49..96 cells: the size classes 64 and 96.  BF16 runs them on the
+matrix cores; FP64 and FP32 run every directional contraction as a tiled
+GEMM on the vector ALU (dense DCT-II / DST-I matrices).  Whole-domain boxes
+(one PEC box covering a 64³ or 96³ domain) make the preconditioner the exact
+inverse up to rounding, so FGMRES converges in one step (FP64) or a few (BF16).
 
-Tolerance: as for the smaller classes, each of the six bf16 contraction
-stages adds at most about 2u (u = 2^-8) of its input's 2-norm and the 3x3
-solve is a contraction: box by box, the owned block's error is below 12u
-times the 2-norm of the box's restricted input."""
+Tolerances.  FP64: max-norm relative 1e-12 against the oracle (each element
+is six dot products of length <= 96, whose rounding stays near 1e-15).
+Reduced precision: each of the six contraction stages rounds its inputs and
+the table entries; the transforms are orthogonal and the 3x3 solve is a
+contraction, so box by box the owned block's error is below k u times the
+2-norm of the box's restricted input.  k = 12 (2u per stage) for bf16, whose
+operands are rounded once per stage; FP32 stages are dense dot products of
+length N accumulated in one chain, whose rounding grows like sqrt(N) u per
+stage: k = 6 * 2 * sqrt(96 / 24) = 24 for the classes up to 96."""
 import numpy as np
 import pytest
 import torch
@@ -63,14 +69,84 @@ def test_bf16_large_boxes_within_bound(n, sub, blk, overlap):
     assert np.all(out[~inputs.unknown_slots(n, n, n)] == 0.0)
 
 
-def test_vector_alu_precisions_reject_large_boxes():
-    for prec in ("fp64", "fp32"):
-        h = api.Handle([dict(nx=64, ny=64, nz=64, c=1.0, sub=(0, 0, 0))], precision=prec, device=DEV)
+LARGE_CASES = [
+    (64, 0, 8, 1),            # one box of 64 cells (class 64), eps blocks
+    (96, 0, 0, 1),            # one box of 96 cells (class 96)
+    (124, 62, 4, 1),          # 8 boxes of 63 cells with overlap (class 64)
+    (100, 50, 0, 2),          # 8 boxes of 52 cells, overlap 2 (class 64)
+    (150, 75, 0, 1),          # 8 boxes of 76 cells (class 96), ragged GEMM tiles
+]
+
+
+def _large(n, sub, blk, overlap, precision):
+    P = inputs.make_problem(dict(n=n, sub=sub, c=2.0, eps_block=blk, seed=n + sub))
+    dom = dict(nx=n, ny=n, nz=n, c=2.0, sub=P["sub"])
+    eps_cell = None
+    if blk:
+        dom.update(eps=P["eps"], eps_block=blk)
+        eps_cell = yee.expand_eps(P["eps"], blk, n, n, n)
+    h = api.Handle([dom], overlap=overlap, precision=precision, device=DEV)
+    z = h.new_vector()
+    h.apply_precond(dev(P["rhs"]), z)
+    ref = ras.ras_apply(P["rhs"], 2.0, P["sub"], overlap, eps_cell)
+    out = host(z, ref.shape)
+    h.close()
+    return P, out, ref
+
+
+@pytest.mark.parametrize("n,sub,blk,overlap", LARGE_CASES)
+def test_fp64_large_boxes_match_oracle(n, sub, blk, overlap):
+    P, out, ref = _large(n, sub, blk, overlap, "fp64")
+    err = np.abs(out - ref).max() / np.abs(ref).max()
+    print(f"fp64 n={n} sub={sub} overlap={overlap}: max rel err {err:.2e}")
+    assert err <= 1e-12
+    assert np.all(out[~inputs.unknown_slots(n, n, n)] == 0.0)
+
+
+@pytest.mark.parametrize("n,sub,blk,overlap", LARGE_CASES)
+def test_fp32_large_boxes_within_bound(n, sub, blk, overlap):
+    P, out, ref = _large(n, sub, blk, overlap, "fp32")
+    errs = []
+    for s in ras.subdomains(n, n, n, P["sub"], overlap):
+        (x0, x1), (y0, y1), (z0, z1) = s["own"]
+        (bx0, bx1), (by0, by1), (bz0, bz1) = s["box"]
+        rin = np.linalg.norm(yee.from_padded(P["rhs"][:, bz0:bz1, by0:by1, bx0:bx1]))
+        d = (out - ref)[:, z0:z1, y0:y1, x0:x1]
+        errs.append(np.linalg.norm(d.ravel()) / rin)
+    u = 2.0**-24
+    print(f"fp32 n={n} sub={sub} overlap={overlap}: worst box error {max(errs):.3e} "
+          f"= {max(errs) / u:.1f} u (bound 24 u)")
+    assert max(errs) < 24 * u
+    assert np.all(out[~inputs.unknown_slots(n, n, n)] == 0.0)
+
+
+def test_boxes_above_96_are_refused():
+    for prec in ("fp64", "fp32", "bf16"):
+        h = api.Handle([dict(nx=128, ny=128, nz=128, c=1.0, sub=(0, 0, 0))], precision=prec,
+                       device=DEV)
         r, z = h.new_vector(), h.new_vector()
         with pytest.raises(api.FlashMPError, match="UNSUPPORTED"):
             h.apply_precond(r, z)
         y = h.new_vector()
         h.curlcurl_apply(r, y)                        # the stencil still works
+        h.close()
+
+
+def test_whole_domain_fp64_is_exact_96():
+    """96³ domain with an eps medium, one box: the preconditioner of a single
+    box covering the domain is A^{-1} when eps is uniform; FGMRES(30) in FP64
+    with it converges in one step."""
+    n, c = 96, 2.0
+    P = inputs.make_problem(dict(n=n, sub=0, c=c, eps_block=0, seed=6))
+    h = api.Handle([dict(nx=n, ny=n, nz=n, c=c)], precision="fp64", device=DEV)
+    x = h.new_vector()
+    info = h.solve(dev(P["rhs"]), x, solver="fgmres", rtol=1e-10, max_iter=20)
+    h.close()
+    assert info["status"] == "FMP_OK" and info["rel_residual_true"] <= 1e-10
+    assert info["iterations"] == 1, info
+    exact = yee.to_padded(transforms.box_solve_transform(yee.from_padded(P["rhs"]), n, n, n, c), n, n, n)
+    xs = host(x, exact.shape)
+    assert np.abs(xs - exact).max() <= 1e-12 * np.abs(exact).max()
 
 
 def test_whole_domain_bf16_fgmres_96():
