@@ -60,6 +60,7 @@ struct IBPlan {
   double* d_WC = nullptr;
   double* d_g = nullptr;
   double* d_hv = nullptr;
+  double* d_part = nullptr;    // partial sums of the C^{-1} h step
   double* d_cinv = nullptr;
   // setup only: pivot block, row and column panels, W^{-1}, unit-box records
   double* d_P = nullptr;

@@ -299,48 +299,74 @@ __global__ __launch_bounds__(256) void k_ib_fill(double* __restrict__ p, long lo
 }
 
 // h = C^{-1} g for up to 16 boxes that share C^{-1}.  C^{-1} is symmetric,
-// so h_i = sum_k C^{-1}[k][i] g_k reads rows of C^{-1}: a wave reads 64
-// consecutive entries of a row, the g values come from LDS.  Item =
-// (matrix, first output row i0, first entry in the grouped box list, count);
-// thread (t % 64) owns output i0 + t % 64 for boxes 4 (t / 64) .. + 3.
-constexpr int kGK = 256;
+// so h_i = sum_k C^{-1}[k][i] g_k streams rows of C^{-1}.  An item (matrix,
+// first output i0, first entry in the grouped box list, count) and a k-range
+// index (blockIdx.y) own outputs i0 .. i0 + 255 for the item's boxes and
+// rows k of one range of kGR: every row is read as one 2 KB contiguous
+// segment (a thread per output column), 16 rows in flight per thread, and
+// the g values of 64 rows at a time sit in LDS.  Partial sums per range go
+// to `part` and k_ib_creduce adds the ranges in a fixed order.
+constexpr int kGC = 256;    // output columns per item
+constexpr int kGR = 1024;   // rows of C^{-1} per k-range
+constexpr int kGG = 64;     // g rows staged per step
 __global__ __launch_bounds__(256) void k_ib_cgemv(const double* __restrict__ Cinv,
                                                   const IBCorrDev* __restrict__ corr,
                                                   const int4* __restrict__ items,
                                                   const int* __restrict__ gbox,
                                                   const BoxDev* __restrict__ boxes,
-                                                  const double* __restrict__ g,
-                                                  double* __restrict__ hv) {
-  __shared__ double gs[16][kGK];
+                                                  const double* __restrict__ g, int ngbox,
+                                                  int m_max, double* __restrict__ part) {
+  __shared__ double gs[kGG][16];
   const int4 it = items[blockIdx.x];
   const IBCorrDev C = corr[it.x];
-  const double* M = Cinv + C.off;
+  const int kb = blockIdx.y * kGR;
+  if (kb >= C.m) return;                          // this matrix has fewer ranges
+  const int ke = min(kb + kGR, C.m);
   const int t = threadIdx.x;
-  const int i = it.y + (t & 63);
-  const int sub = t >> 6;
+  const int i = it.y + t;
+  const bool valid = i < C.m;
+  const double* M = Cinv + C.off + (valid ? i : 0);
   const int nb = it.w;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < C.m; k0 += kGK) {
-    const int kc = min(kGK, C.m - k0);
-    for (int e = t; e < 16 * kGK; e += 256) {
-      const int b = e / kGK, kk = e - b * kGK;
-      gs[b][kk] = (b < nb && kk < kc) ? g[boxes[gbox[it.z + b]].g_off + k0 + kk] : 0.0;
+  double acc[16];
+#pragma unroll
+  for (int b = 0; b < 16; ++b) acc[b] = 0.0;
+  for (int k0 = kb; k0 < ke; k0 += kGG) {
+    const int kc = min(kGG, ke - k0);
+    for (int e = t; e < kGG * 16; e += 256) {
+      const int kk = e >> 4, b = e & 15;
+      gs[kk][b] = (b < nb && kk < kc) ? g[boxes[gbox[it.z + b]].g_off + k0 + kk] : 0.0;
     }
     __syncthreads();
-    if (i < C.m) {
-      const double* Mk = M + (long long)k0 * C.mp + i;
-#pragma unroll 4
-      for (int kk = 0; kk < kc; ++kk) {
-        const double cv = Mk[(long long)kk * C.mp];
+#pragma unroll 16
+    for (int kk = 0; kk < kc; ++kk) {
+      const double cv = M[(long long)(k0 + kk) * C.mp];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[j] = __builtin_fma(cv, gs[4 * sub + j][kk], acc[j]);
-      }
+      for (int b = 0; b < 16; ++b) acc[b] = __builtin_fma(cv, gs[kk][b], acc[b]);
     }
     __syncthreads();
   }
-  if (i < C.m)
-    for (int j = 0; j < 4; ++j)
-      if (4 * sub + j < nb) hv[boxes[gbox[it.z + 4 * sub + j]].g_off + i] = acc[j];
+  if (!valid) return;
+  for (int b = 0; b < nb; ++b)
+    part[((long long)blockIdx.y * ngbox + it.z + b) * m_max + i] = acc[b];
+}
+
+// h[box][i] = sum over the k-ranges of the partial sums, in range order
+__global__ __launch_bounds__(256) void k_ib_creduce(const double* __restrict__ part,
+                                                    const IBCorrDev* __restrict__ corr,
+                                                    const int* __restrict__ gbox,
+                                                    const BoxDev* __restrict__ boxes,
+                                                    int ngbox, int m_max,
+                                                    double* __restrict__ hv) {
+  const int e = blockIdx.y;
+  const BoxDev& B = boxes[gbox[e]];
+  const int m = B.m;
+  const int nr = (m + kGR - 1) / kGR;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < m; i += gridDim.x * 256) {
+    double s = 0.0;
+    for (int r = 0; r < nr; ++r) s += part[((long long)r * ngbox + e) * m_max + i];
+    hv[B.g_off + i] = s;
+  }
+  (void)corr;
 }
 
 // ---------------------------------------------------------------- setup kernels
@@ -394,21 +420,21 @@ __global__ __launch_bounds__(256) void k_gj_pivot(const double* __restrict__ A, 
   for (int e = t; e < kGB * kGB; e += 256) a[e / kGB][e % kGB] = A[(long long)(k0 + e / kGB) * mp + k0 + e % kGB];
   __syncthreads();
   for (int p = 0; p < kGB; ++p) {
-    const double piv = a[p][p];
+    const double rp = 1.0 / a[p][p];               // one division per thread and step
     double upd[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int e = t + 256 * r, i = e / kGB, j = e % kGB;
-      upd[r] = (i != p && j != p) ? a[i][j] - a[i][p] * a[p][j] / piv : 0.0;
+      upd[r] = (i != p && j != p) ? a[i][j] - a[i][p] * (a[p][j] * rp) : 0.0;
     }
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int e = t + 256 * r, i = e / kGB, j = e % kGB;
       if (i != p && j != p) a[i][j] = upd[r];
-      else if (i == p && j == p) a[i][j] = 1.0 / piv;
-      else if (i == p) a[i][j] = a[i][j] / piv;
-      else a[i][j] = -a[i][j] / piv;
+      else if (i == p && j == p) a[i][j] = rp;
+      else if (i == p) a[i][j] = a[i][j] * rp;
+      else a[i][j] = -a[i][j] * rp;
     }
     __syncthreads();
   }
@@ -715,20 +741,26 @@ fmp_status ib_prepare(fmp_ctx* h) {
     cl.nb = (int)P.work_b.size() - cl.b0;
     if (cl.na) P.cls.push_back(cl);
   }
-  // C^{-1} h items: boxes grouped by matrix, 16 at a time, 64 rows per item
+  // C^{-1} h items: boxes grouped by matrix, 16 at a time, kGC outputs per item
   for (size_t k = 0; k < P.corr.size(); ++k) {
     const int first = (int)P.gbox.size();
     for (size_t bi = 0; bi < P.boxes.size(); ++bi)
       if (P.boxes[bi].corr == (int)k) P.gbox.push_back((int)bi);
     const int cnt = (int)P.gbox.size() - first;
     for (int b0 = 0; b0 < cnt; b0 += 16)
-      for (int i0 = 0; i0 < P.corr[k].m; i0 += 64)
+      for (int i0 = 0; i0 < P.corr[k].m; i0 += kGC)
         P.gemv.push_back(make_int4((int)k, i0, first + b0, std::min(16, cnt - b0)));
   }
   // setup batches of unit solves reuse the W_E + W_C region
   P.unit_batch = std::max(1, std::min(P.m_max, 128));
   P.stage_elems = std::max(2 * P.w_elems, (long long)P.unit_batch * ((3 * vmax + 7) / 8 * 8));
   return FMP_OK;
+}
+
+// partial sums of the C^{-1} h step: k-ranges x grouped boxes x m_max
+static size_t gemv_part_elems(const IBPlan& P) {
+  const size_t nr = (size_t)(P.m_max + kGR - 1) / kGR;
+  return nr * P.gbox.size() * (size_t)P.m_max;
 }
 
 size_t ib_workspace_bytes(const fmp_ctx* h) {
@@ -744,6 +776,7 @@ size_t ib_workspace_bytes(const fmp_ctx* h) {
   b += al(std::max<size_t>(P.gbox.size(), 1) * 4);
   b += al((size_t)P.stage_elems * 8);
   b += 2 * al((size_t)P.g_elems * 8);
+  b += al(std::max<size_t>(gemv_part_elems(P), 1) * 8);
   b += al(std::max<long long>(P.cinv_elems, 1) * 8);
   // setup only
   b += al((size_t)kGB * kGB * 8);
@@ -775,6 +808,7 @@ fmp_status ib_bind(fmp_ctx* h, char* base, hipStream_t s) {
   P.d_WC = stage + P.w_elems;
   P.d_g = (double*)take((size_t)P.g_elems * 8);
   P.d_hv = (double*)take((size_t)P.g_elems * 8);
+  P.d_part = (double*)take(std::max<size_t>(gemv_part_elems(P), 1) * 8);
   P.d_cinv = (double*)take(std::max<long long>(P.cinv_elems, 1) * 8);
   P.d_P = (double*)take((size_t)kGB * kGB * 8);
   P.d_Row = (double*)take((size_t)std::max(P.mp_max, kGB) * kGB * 8);
@@ -889,8 +923,11 @@ fmp_status ib_apply(fmp_ctx* h, const double* r, double* z, hipStream_t s) {
     // g = Q^T E, h = C^{-1} g, W_C = Q h
     const int mblk = std::max(1, std::min(64, (P.m_max + 255) / 256));
     hipLaunchKernelGGL(k_ib_qgather, dim3(mblk, nbox), dim3(256), 0, s, P.d_WE, P.d_boxes, P.d_qidx, P.d_g);
-    hipLaunchKernelGGL(k_ib_cgemv, dim3((int)P.gemv.size()), dim3(256), 0, s, P.d_cinv, P.d_corr,
-                       P.d_gemv, P.d_gbox, P.d_boxes, P.d_g, P.d_hv);
+    const int nr = (P.m_max + kGR - 1) / kGR, ngb = (int)P.gbox.size();
+    hipLaunchKernelGGL(k_ib_cgemv, dim3((int)P.gemv.size(), nr), dim3(256), 0, s, P.d_cinv,
+                       P.d_corr, P.d_gemv, P.d_gbox, P.d_boxes, P.d_g, ngb, P.m_max, P.d_part);
+    hipLaunchKernelGGL(k_ib_creduce, dim3(std::min(64, (P.m_max + 255) / 256), ngb), dim3(256), 0,
+                       s, P.d_part, P.d_corr, P.d_gbox, P.d_boxes, ngb, P.m_max, P.d_hv);
     hipLaunchKernelGGL(k_ib_fill, dim3(blocks_for(P.w_elems)), dim3(256), 0, s, P.d_WC, P.w_elems, 0.0);
     hipLaunchKernelGGL(k_ib_qscatter, dim3(mblk, nbox), dim3(256), 0, s, P.d_hv, P.d_boxes, P.d_qidx, P.d_WC);
     IBCHK(hipGetLastError());

@@ -107,3 +107,33 @@ def test_index_block_workspace_query(L):
         assert st == -6
     st, _ = _size_pd(L, [_desc(64, 32)], _lib.PrecondDesc(0, 0, 0, 0, 0, 2))
     assert st == -1
+
+
+def test_ctypes_structs_match_the_c_layout(tmp_path):
+    """Every struct the binding passes across the ABI has the size and field
+    offsets the C compiler gives it (a mismatch would make the library read
+    or write past the caller's host memory)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"fmp_domain_desc": _lib.DomainDesc, "fmp_precond_desc": _lib.PrecondDesc,
+               "fmp_tune_entry": _lib.TuneEntry, "fmp_solve_opts": _lib.SolveOpts,
+               "fmp_solve_info": _lib.SolveInfo}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "flashmp.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("  return 0;\n}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == C.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
