@@ -201,26 +201,41 @@ fmp_status fmp_curlcurl_apply(fmp_handle h, const double* x, double* y, void* st
  * r, z: device, must not overlap. */
 fmp_status fmp_apply_precond(fmp_handle h, const double* r, double* z, void* stream);
 
-/* One measured candidate of fmp_autotune. */
+/* One measured candidate of fmp_autotune: a preconditioner launch plan
+ * (stencil_ty = 0) or a stencil tile height (stencil_ty > 0, the other plan
+ * fields 0). */
 typedef struct {
   int32_t batch_boxes;   /* boxes per batch (staging reused batch after batch)  */
   int32_t streams;       /* 1: batches in order; 2: consecutive batches on two
                             private streams with two staging buffers (overlap) */
   int32_t slab_order;    /* gather/scatter work order: 0 box by box, 1 slab by
                             slab across the batch's boxes (shared halo lines)  */
-  double apply_ms;       /* mean preconditioner apply time (HIP events)         */
-  int32_t chosen;        /* 1 for the candidate the handle now uses             */
+  double apply_ms;       /* mean time of one preconditioner apply, or of one
+                            fmp_curlcurl_apply for a stencil candidate (HIP
+                            events)                                             */
+  int32_t chosen;        /* 1 for the candidates the handle now uses            */
+  int32_t stencil_ty;    /* stencil tile 64 x stencil_ty (4, 8, 16), or 0       */
+  int32_t cached;        /* 1: the plan came from the FMP_TUNE_CACHE file       */
 } fmp_tune_entry;
 
-/* Autotuner of the preconditioner's launch plan: times fmp_apply_precond(r, z)
- * as plain launch sequences (three applies after a warm-up) for
- * every candidate batch size (16 .. 1024 boxes and all boxes, per size class),
- * stream count and gather work order, and keeps the fastest plan.  Every plan
- * computes the same z bit for bit; only the schedule changes.  Requires a
- * handle set up with batch_boxes = -1 (else FMP_ERR_UNSUPPORTED).  r, z:
- * device vectors (not overlapping); z is overwritten.  entries: optional host
- * array of max_entries records; *n_entries (may be NULL) gets the count
- * written.  Synchronises the stream. */
+/* Autotuner of the launch plans.  Preconditioner: times fmp_apply_precond(r, z)
+ * as plain launch sequences (three applies after a warm-up) for every
+ * candidate batch size (16 .. 1024 boxes and all boxes, per size class),
+ * stream count and gather work order.  Stencil: times fmp_curlcurl_apply(r, z)
+ * (five applies after a warm-up) for tiles of 64 x 4, 64 x 8 and 64 x 16
+ * columns.  Keeps the fastest of each.  Every plan computes the same results
+ * bit for bit; only the schedule changes.
+ * Persistent cache: if the environment variable FMP_TUNE_CACHE names a file,
+ * a record for this handle's key (library revision, device, precision,
+ * overlap, learned part, every domain's size and subdomain split) is looked
+ * up there first; a hit applies the recorded plan and times only it (the
+ * returned entries say cached = 1), a miss tunes and appends the record.  The
+ * file is plain text, one record per line; concurrent writers are not
+ * coordinated.
+ * Requires a handle set up with batch_boxes = -1 (else FMP_ERR_UNSUPPORTED).
+ * r, z: device vectors (not overlapping); z is overwritten.  entries:
+ * optional host array of max_entries records; *n_entries (may be NULL) gets
+ * the count written.  Synchronises the stream. */
 fmp_status fmp_autotune(fmp_handle h, const double* r, double* z, fmp_tune_entry* entries,
                         int32_t max_entries, int32_t* n_entries, void* stream);
 

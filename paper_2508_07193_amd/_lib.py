@@ -33,7 +33,8 @@ class PrecondDesc(C.Structure):
 
 class TuneEntry(C.Structure):
     _fields_ = [("batch_boxes", C.c_int32), ("streams", C.c_int32), ("slab_order", C.c_int32),
-                ("apply_ms", C.c_double), ("chosen", C.c_int32)]
+                ("apply_ms", C.c_double), ("chosen", C.c_int32), ("stencil_ty", C.c_int32),
+                ("cached", C.c_int32)]
 
 
 class SolveOpts(C.Structure):

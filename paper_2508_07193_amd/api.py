@@ -157,7 +157,8 @@ def fmp_autotune(h, r=None, z=None, stream=None):
     _check(_lib.load().fmp_autotune(h.h, _ptr(r), _ptr(z), ent, 64, C.byref(n), _stream(stream)),
            "fmp_autotune", h.h)
     return [dict(batch_boxes=e.batch_boxes, streams=e.streams, slab_order=e.slab_order,
-                 apply_ms=e.apply_ms, chosen=bool(e.chosen)) for e in ent[:n.value]]
+                 apply_ms=e.apply_ms, chosen=bool(e.chosen), stencil_ty=e.stencil_ty,
+                 cached=bool(e.cached)) for e in ent[:n.value]]
 
 
 def solve_opts(solver="fgmres", restart=30, max_iter=500, rtol=1e-8, precond=True, check_every=1,

@@ -288,7 +288,8 @@ static fmp_status precond_launches(fmp_ctx* h, const double* r, double* z, hipSt
 }
 
 static fmp_status spmv(fmp_ctx* h, const double* x, double* y, hipStream_t s) {
-  HIPCHK(h, launch_curlcurl(x, y, h->d_doms, h->d_tiles, h->ntiles, h->d_eps, s));
+  HIPCHK(h, launch_curlcurl(kStencilTYs[h->stencil_v], x, y, h->d_doms, h->d_tiles, h->ntiles,
+                            h->d_eps, s));
   return FMP_OK;
 }
 
@@ -299,6 +300,56 @@ hipError_t fmp_coarse_resid_test(fmp_ctx* h, const double* v, const double* w, d
                             hipStream_t s);
 size_t fmp_coarse_workspace(int nsub, int hidden_max);
 void fmp_coarse_bind(fmp_ctx* h, void* base);
+
+// ---- persistent autotuner cache ---------------------------------------------
+// Key: what the plan's timing depends on (library revision, device, precision,
+// overlap, learned part, and every domain's size and subdomain split).
+static std::string tune_key(const fmp_ctx* h) {
+  std::string k = "flashmp-plan-2";
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+    k += std::string("|") + prop.gcnArchName;
+  k += "|p" + std::to_string(h->prec) + "|o" + std::to_string(h->overlap) + "|l" +
+       std::to_string((int)h->use_learned);
+  for (const DomainDev& D : h->doms)
+    k += "|" + std::to_string(D.nx) + "x" + std::to_string(D.ny) + "x" + std::to_string(D.nz) +
+         "/" + std::to_string(D.sx) + "x" + std::to_string(D.sy) + "x" + std::to_string(D.sz);
+  for (char& c : k)
+    if (c == ' ' || c == '\n' || c == '\t') c = '_';
+  return k;
+}
+
+static bool tune_cache_find(const char* path, const std::string& key, int* batch, int* ns,
+                            int* slab, int* ty) {
+  FILE* f = fopen(path, "r");
+  if (!f) return false;
+  char line[8192];
+  bool found = false;
+  while (fgets(line, sizeof line, f)) {
+    char k[8192];
+    int b, n, so, t;
+    if (sscanf(line, "%8191s %d %d %d %d", k, &b, &n, &so, &t) == 5 && key == k &&
+        b > 0 && n >= 1 && n <= fmp_ctx::kMaxStreams && (so == 0 || so == 1)) {
+      bool ty_ok = false;
+      for (int v = 0; v < kNumStencilTY; ++v) ty_ok = ty_ok || kStencilTYs[v] == t;
+      if (ty_ok) {                                // the last matching record wins
+        *batch = b; *ns = n; *slab = so; *ty = t;
+        found = true;
+      }
+    }
+  }
+  fclose(f);
+  return found;
+}
+
+static void tune_cache_add(const char* path, const std::string& key, int batch, int ns, int slab,
+                           int ty) {
+  FILE* f = fopen(path, "a");
+  if (!f) return;
+  fprintf(f, "%s %d %d %d %d\n", key.c_str(), batch, ns, slab, ty);
+  fclose(f);
+}
 
 // Detail of the last failed call that has no handle, per host thread.
 static thread_local std::string g_free_err;
@@ -572,14 +623,20 @@ fmp_status fmp_setup_subdomains(const fmp_domain_desc* domains, int32_t n_domain
   const long long w_batch_max = h->w_cap;
 
   // ---- stencil tiles
+  // (one list per tile height, back to back)
   std::vector<StencilTile> tiles;
-  for (int d = 0; d < n_domains; ++d) {
-    const DomainDev& D = h->doms[d];
-    for (int z0 = 0; z0 < D.nz; z0 += kStencilZC)
-      for (int y0 = 0; y0 < D.ny; y0 += kStencilTY)
-        for (int x0 = 0; x0 < D.nx; x0 += kStencilTX) tiles.push_back({d, x0, y0, z0});
+  int tile0[kNumStencilTY];
+  for (int v = 0; v < kNumStencilTY; ++v) {
+    tile0[v] = (int)tiles.size();
+    for (int d = 0; d < n_domains; ++d) {
+      const DomainDev& D = h->doms[d];
+      for (int z0 = 0; z0 < D.nz; z0 += kStencilZC)
+        for (int y0 = 0; y0 < D.ny; y0 += kStencilTYs[v])
+          for (int x0 = 0; x0 < D.nx; x0 += kStencilTX) tiles.push_back({d, x0, y0, z0});
+    }
+    h->ntiles_v[v] = (int)tiles.size() - tile0[v];
   }
-  h->ntiles = (int)tiles.size();
+  h->ntiles = h->ntiles_v[h->stencil_v];
 
   // ---- workspace layout
   const size_t tsz = (h->prec == FMP_FP64) ? 8 : (h->prec == FMP_FP32 ? 4 : 2);
@@ -631,7 +688,8 @@ fmp_status fmp_setup_subdomains(const fmp_domain_desc* domains, int32_t n_domain
   char* base = (char*)ws;
   h->d_doms = (DomainDev*)(base + o_doms);
   h->d_boxes = (BoxDev*)(base + o_boxes);
-  h->d_tiles = (StencilTile*)(base + o_tiles);
+  for (int v = 0; v < kNumStencilTY; ++v) h->d_tiles_v[v] = (StencilTile*)(base + o_tiles) + tile0[v];
+  h->d_tiles = h->d_tiles_v[h->stencil_v];
   h->d_eps = (double*)(base + o_eps);
   h->d_tab = base + o_tab;
   h->d_sig32 = (float*)(base + o_sig32);
@@ -667,7 +725,7 @@ fmp_status fmp_setup_subdomains(const fmp_domain_desc* domains, int32_t n_domain
                             hipMemcpyHostToDevice, s));
   HIPCHK(hp, hipMemcpyAsync(h->d_boxes, h->boxes.data(), h->boxes.size() * sizeof(BoxDev),
                             hipMemcpyHostToDevice, s));
-  HIPCHK(hp, hipMemcpyAsync(h->d_tiles, tiles.data(), tiles.size() * sizeof(StencilTile),
+  HIPCHK(hp, hipMemcpyAsync(h->d_tiles_v[0], tiles.data(), tiles.size() * sizeof(StencilTile),
                             hipMemcpyHostToDevice, s));
   if (!eps_all.empty())
     HIPCHK(hp, hipMemcpyAsync(h->d_eps, eps_all.data(), eps_all.size() * 8, hipMemcpyHostToDevice, s));
@@ -766,11 +824,12 @@ fmp_status fmp_autotune(fmp_handle h, const double* r, double* z, fmp_tune_entry
   for (int b : {16, 32, 64, 128, 256, 512, 1024})
     if (b < nbox) batches.push_back(b);
   batches.push_back(nbox);
-  struct Cand { int batch, ns, slab; double ms; };
+  struct Cand { int batch, ns, slab, ty; double ms; };   // ty > 0: a stencil candidate
   std::vector<Cand> cands;
   for (int b : batches)
     for (int ns = 1; ns <= std::min(h->n_wbuf, fmp_ctx::kMaxStreams); ++ns)
-      for (int so = 0; so < 2; ++so) cands.push_back({b, ns, so, 0.0});
+      for (int so = 0; so < 2; ++so) cands.push_back({b, ns, so, 0, 0.0});
+  for (int v = 0; v < kNumStencilTY; ++v) cands.push_back({0, 0, 0, kStencilTYs[v], 0.0});
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIPCHK(h, hipEventCreate(&e0));
   HIPCHK(h, hipEventCreate(&e1));
@@ -796,35 +855,81 @@ fmp_status fmp_autotune(fmp_handle h, const double* r, double* z, fmp_tune_entry
     HIPCHK(h, hipStreamSynchronize(s));
     return FMP_OK;
   };
-  fmp_status st = FMP_OK;
-  for (Cand& c : cands) {
-    if ((st = use(c.batch, c.ns, c.slab)) != FMP_OK) break;
-    if (c.ns > 1 && (int)h->launches.size() < c.ns) { c.ms = -1.0; continue; }   // no more overlap
-    // candidates are timed as plain launch sequences (no capture per
-    // candidate); a graph-mode handle captures the chosen plan on first use
-    if ((st = precond_launches(h, r, z, s, coarse)) != FMP_OK) break;   // warm up
+  auto use_stencil = [&](int ty) {
+    for (int v = 0; v < kNumStencilTY; ++v)
+      if (kStencilTYs[v] == ty) h->stencil_v = v;
+    h->d_tiles = h->d_tiles_v[h->stencil_v];
+    h->ntiles = h->ntiles_v[h->stencil_v];
+  };
+  // mean time of `reps` runs of fn after one warm-up
+  auto time_of = [&](auto fn, int reps, double* ms_out) -> fmp_status {
+    fmp_status st = fn();
+    if (st != FMP_OK) return st;
     HIPCHK(h, hipEventRecord(e0, s));
-    constexpr int kReps = 3;
-    for (int k = 0; k < kReps && st == FMP_OK; ++k) st = precond_launches(h, r, z, s, coarse);
-    if (st != FMP_OK) break;
+    for (int k = 0; k < reps && st == FMP_OK; ++k) st = fn();
+    if (st != FMP_OK) return st;
     HIPCHK(h, hipEventRecord(e1, s));
     HIPCHK(h, hipEventSynchronize(e1));
     float ms = 0.f;
     HIPCHK(h, hipEventElapsedTime(&ms, e0, e1));
-    c.ms = ms / kReps;
+    *ms_out = ms / reps;
+    return FMP_OK;
+  };
+  auto apply_once = [&]() { return precond_launches(h, r, z, s, coarse); };
+  auto spmv_once = [&]() { return spmv(h, r, z, s); };
+
+  // persistent plan cache: FMP_TUNE_CACHE names a text file of
+  // "key batch streams slab_order stencil_ty" lines
+  const std::string key = tune_key(h);
+  const char* cache_path = getenv("FMP_TUNE_CACHE");
+  Cand hit{0, 0, 0, 0, -1.0};
+  bool cached = false;
+  if (cache_path && *cache_path) cached = tune_cache_find(cache_path, key, &hit.batch, &hit.ns,
+                                                           &hit.slab, &hit.ty);
+  fmp_status st = FMP_OK;
+  const Cand* best = nullptr;
+  const Cand* best_st = nullptr;
+  if (cached) {
+    cands.assign({Cand{hit.batch, hit.ns, hit.slab, 0, 0.0}, Cand{0, 0, 0, hit.ty, 0.0}});
+    best = &cands[0];
+    best_st = &cands[1];
+  }
+  for (Cand& c : cands) {
+    if (c.ty > 0) {                               // stencil tile height
+      use_stencil(c.ty);
+      if ((st = time_of(spmv_once, 5, &c.ms)) != FMP_OK) break;
+      continue;
+    }
+    if ((st = use(c.batch, c.ns, c.slab)) != FMP_OK) break;
+    if (c.ns > 1 && (int)h->launches.size() < c.ns) { c.ms = -1.0; continue; }   // no more overlap
+    // candidates are timed as plain launch sequences (no capture per
+    // candidate); a graph-mode handle captures the chosen plan on first use
+    if ((st = time_of(apply_once, 3, &c.ms)) != FMP_OK) break;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (st != FMP_OK) return st;
-  const Cand* best = nullptr;
-  for (const Cand& c : cands)
-    if (c.ms >= 0.0 && (!best || c.ms < best->ms)) best = &c;
+  if (!cached) {
+    for (const Cand& c : cands) {
+      if (c.ms < 0.0) continue;
+      if (c.ty == 0 && (!best || c.ms < best->ms)) best = &c;
+      if (c.ty > 0 && (!best_st || c.ms < best_st->ms)) best_st = &c;
+    }
+  }
+  if (!best || !best_st) {
+    h->err = "fmp_autotune: no plan could be timed";
+    return FMP_ERR_UNSUPPORTED;
+  }
   if ((st = use(best->batch, best->ns, best->slab)) != FMP_OK) return st;
+  use_stencil(best_st->ty);
+  if (!cached && cache_path && *cache_path)
+    tune_cache_add(cache_path, key, best->batch, best->ns, best->slab, best_st->ty);
   int k = 0;
   for (const Cand& c : cands) {
     if (c.ms < 0.0) continue;
     if (entries && k < max_entries)
-      entries[k] = fmp_tune_entry{c.batch, c.ns, c.slab, c.ms, &c == best};
+      entries[k] = fmp_tune_entry{c.batch, c.ns, c.slab, c.ms, (&c == best || &c == best_st),
+                                  c.ty, cached ? 1 : 0};
     ++k;
   }
   if (n_entries) *n_entries = std::min(k, max_entries);

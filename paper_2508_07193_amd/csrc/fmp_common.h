@@ -86,12 +86,16 @@ __host__ __device__ inline long long box_wvol(const BoxDev& B, bool mfma) {
   return mfma ? (long long)B.nx * B.ny * B.wzp : B.vol;
 }
 
-// Stencil tile: 64 x 8 columns marching over kStencilZC planes of one domain.
+// Stencil tile: 64 x TY columns marching over kStencilZC planes of one domain;
+// the tile heights fmp_autotune chooses from, and the default.
 struct StencilTile {
   int dom, x0, y0, z0;
 };
 
-constexpr int kStencilTX = 64, kStencilTY = 8, kStencilZC = 64;
+constexpr int kStencilTX = 64, kStencilZC = 64;
+constexpr int kStencilTYs[] = {4, 8, 16};
+constexpr int kNumStencilTY = 3;
+constexpr int kStencilDefault = 1;   // 64 x 8
 
 // Workgroups of a launch are dealt to the 8 XCDs round-robin (block b runs on
 // XCD b % 8).  xcd_remap(b, nb) renumbers them so that each XCD works through
@@ -120,7 +124,7 @@ struct SegDev {
 };
 
 // ---- launchers (defined in the .hip files) ---------------------------------
-hipError_t launch_curlcurl(const double* x, double* y, const DomainDev* doms,
+hipError_t launch_curlcurl(int ty, const double* x, double* y, const DomainDev* doms,
                            const StencilTile* tiles, int ntiles, const double* eps,
                            hipStream_t s);
 

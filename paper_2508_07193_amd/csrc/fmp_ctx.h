@@ -93,7 +93,10 @@ struct fmp_ctx {
   bool precond_ok = true;      // every box side has a compiled transform class
   int nsub = 0;
   long long len = 0;
-  int ntiles = 0;
+  int ntiles = 0;                      // stencil tiles of the chosen tile height
+  int stencil_v = fmp::kStencilDefault;
+  int ntiles_v[fmp::kNumStencilTY] = {0, 0, 0};
+  StencilTile* d_tiles_v[fmp::kNumStencilTY] = {nullptr, nullptr, nullptr};
   // device regions inside the workspace
   DomainDev* d_doms = nullptr;
   BoxDev* d_boxes = nullptr;

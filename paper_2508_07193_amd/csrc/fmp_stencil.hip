@@ -10,8 +10,10 @@
 // and the E_y, E_z rows follow by the cyclic relabelling x -> y -> z -> x.
 // Values outside the domain or on a wall slot are zero.
 //
-// Mapping: a workgroup owns a 64 x 8 tile of (i, j) columns and marches over
-// kStencilZC = 64 z-planes (the fastest of the tile shapes swept at 256^3).
+// Mapping: a workgroup owns a 64 x TY tile of (i, j) columns and marches over
+// kStencilZC = 64 z-planes; TY is 4, 8 or 16 (256, 512 or 1024 threads),
+// chosen by fmp_autotune (8 by default, the fastest of the shapes swept at
+// 256^3).
 // Three rolling LDS planes (k-1, k, k+1) of all three components, with a
 // one-cell halo in x and y, are filled by coalesced loads
 // that zero wall slots and out-of-domain cells once, so the stencil itself
@@ -27,14 +29,16 @@
 namespace fmp {
 namespace {
 
-constexpr int TX = kStencilTX, TY = kStencilTY;
-constexpr int HX = TX + 2, HY = TY + 2;   // tile with halo
+constexpr int TX = kStencilTX;
+constexpr int HX = TX + 2;                // tile with halo in x
 
+template <int TY>
 __global__ __launch_bounds__(TX * TY) void k_curlcurl(const double* __restrict__ x,
                                                       double* __restrict__ y,
                                                       const DomainDev* __restrict__ doms,
                                                       const StencilTile* __restrict__ tiles,
                                                       int ntiles, const double* __restrict__ eps) {
+  constexpr int HY = TY + 2;                  // tile with halo in y
   __shared__ double P[3][3][HY][HX];          // [slot][component][j][i]
   __shared__ double E[2][TY + 1][TX + 1];     // cell eps, [slot][j][i] for cells j0-1.., i0-1..
   const StencilTile T = tiles[xcd_remap(blockIdx.x, ntiles)];
@@ -159,12 +163,26 @@ __global__ __launch_bounds__(TX * TY) void k_curlcurl(const double* __restrict__
 
 }  // namespace
 
-hipError_t launch_curlcurl(const double* x, double* y, const DomainDev* doms,
+hipError_t launch_curlcurl(int ty, const double* x, double* y, const DomainDev* doms,
                            const StencilTile* tiles, int ntiles, const double* eps,
                            hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_curlcurl, dim3(ntiles), dim3(TX * TY), 0, s, x, y, doms, tiles, ntiles,
-                     eps);
+  switch (ty) {
+    case 4:
+      hipLaunchKernelGGL(k_curlcurl<4>, dim3(ntiles), dim3(TX * 4), 0, s, x, y, doms, tiles,
+                         ntiles, eps);
+      break;
+    case 8:
+      hipLaunchKernelGGL(k_curlcurl<8>, dim3(ntiles), dim3(TX * 8), 0, s, x, y, doms, tiles,
+                         ntiles, eps);
+      break;
+    case 16:
+      hipLaunchKernelGGL(k_curlcurl<16>, dim3(ntiles), dim3(TX * 16), 0, s, x, y, doms, tiles,
+                         ntiles, eps);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -412,6 +412,8 @@ __global__ __launch_bounds__(256) void k_ib_symm(double* __restrict__ A, int mp)
 //   P = A_kk^{-1};  Row = P A_k,: ;  Col = A_:,k (copy);
 //   A_ij -= Col_i Row_j (i, j != k);  A_kj = Row_j;  A_ik = -Col_i P;  A_kk = P.
 constexpr int kGB = 64;
+// rank-64 updates of the inversion on the matrix cores (FP64 MFMA) or the vector ALU
+constexpr bool kGJMatrixCores = true;
 
 __global__ __launch_bounds__(256) void k_gj_pivot(const double* __restrict__ A, int mp, int k0,
                                                   double* __restrict__ P) {
@@ -513,6 +515,52 @@ __global__ __launch_bounds__(256) void k_gj_update(double* __restrict__ A, int m
     for (int c = 0; c < 4; ++c) {
       const long long idx = (r0 + ti * 4 + r) * mp + c0 + tj + 16 * c;
       A[idx] = (J == kb) ? -acc[r][c] : A[idx] - acc[r][c];
+    }
+}
+
+// The same update on the matrix cores: v_mfma_f64_16x16x4f64 with lane l
+// holding A[l % 16][l / 16] and B[l / 16][l % 16] and the accumulator's
+// element i at D[4 i + l / 16][l % 16] (measured on gfx950).  Wave w computes rows 16 w .. + 15
+// of the 64 x 64 tile against its four 16-column tiles, 16 k-steps of 4.
+typedef double d4_t __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void k_gj_update_mfma(double* __restrict__ A, int mp, int kb,
+                                                        const double* __restrict__ P,
+                                                        const double* __restrict__ Row,
+                                                        const double* __restrict__ Col) {
+  __shared__ double cl[kGB][kGB + 1], rw[kGB][kGB + 1];
+  const int I = blockIdx.y, J = blockIdx.x;
+  const int t = threadIdx.x;
+  const long long r0 = (long long)I * kGB, c0 = (long long)J * kGB;
+  if (I == kb) {                                  // block row k: Row (or P on the diagonal)
+    for (int e = t; e < kGB * kGB; e += 256) {
+      const int i = e / kGB, j = e % kGB;
+      A[(r0 + i) * mp + c0 + j] = (J == kb) ? P[e] : Row[(long long)i * mp + c0 + j];
+    }
+    return;
+  }
+  for (int e = t; e < kGB * kGB; e += 256) {
+    const int i = e / kGB, j = e % kGB;
+    cl[i][j] = Col[(r0 + i) * kGB + j];
+    rw[i][j] = (J == kb) ? P[e] : Row[(long long)i * mp + c0 + j];
+  }
+  __syncthreads();
+  const int w = t >> 6, l = t & 63, lr = l & 15, lk = l >> 4;
+  d4_t acc[4];
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) acc[nt] = d4_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+  for (int ks = 0; ks < kGB / 4; ++ks) {
+    const double a = cl[16 * w + lr][4 * ks + lk];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+      acc[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, rw[4 * ks + lk][16 * nt + lr], acc[nt], 0, 0, 0);
+  }
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const long long idx = (r0 + 16 * w + 4 * i + lk) * mp + c0 + 16 * nt + lr;
+      A[idx] = (J == kb) ? -acc[nt][i] : A[idx] - acc[nt][i];
     }
 }
 
@@ -891,8 +939,12 @@ fmp_status ib_bind(fmp_ctx* h, char* base, hipStream_t s) {
       hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(256), 0, s, Cm, C.mp, kb * kGB, P.d_P);
       hipLaunchKernelGGL(k_gj_panels, dim3(nblk), dim3(256), 0, s, Cm, C.mp, kb * kGB, P.d_P,
                          P.d_Row, P.d_Col);
-      hipLaunchKernelGGL(k_gj_update, dim3(nblk, nblk), dim3(256), 0, s, Cm, C.mp, kb, P.d_P,
-                         P.d_Row, P.d_Col);
+      if (kGJMatrixCores)
+        hipLaunchKernelGGL(k_gj_update_mfma, dim3(nblk, nblk), dim3(256), 0, s, Cm, C.mp, kb,
+                           P.d_P, P.d_Row, P.d_Col);
+      else
+        hipLaunchKernelGGL(k_gj_update, dim3(nblk, nblk), dim3(256), 0, s, Cm, C.mp, kb, P.d_P,
+                           P.d_Row, P.d_Col);
     }
     hipLaunchKernelGGL(k_ib_symm, sg, dim3(256), 0, s, Cm, C.mp);
     IBCHK(hipGetLastError());

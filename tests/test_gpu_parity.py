@@ -489,18 +489,103 @@ def test_autotune_keeps_results_bitwise():
     r = torch.cat([dev(inputs.normal_rhs(rng, n, n, n)) for n, _, _ in spec])
     for prec, graph in (("fp32", True), ("fp64", False)):
         h = api.Handle(doms, precision=prec, device=DEV, batch_boxes=-1, use_graph=graph)
-        z0 = h.new_vector()
+        z0, y0 = h.new_vector(), h.new_vector()
         h.apply_precond(r, z0)
+        h.curlcurl_apply(r, y0)
         tune = h.autotune(r, h.new_vector())
-        assert sum(t["chosen"] for t in tune) == 1 and all(t["apply_ms"] > 0 for t in tune)
-        assert {t["streams"] for t in tune} == {1, 2}
-        assert {t["slab_order"] for t in tune} == {0, 1}
-        z1 = h.new_vector()
+        plans = [t for t in tune if t["stencil_ty"] == 0]
+        tiles = [t for t in tune if t["stencil_ty"] > 0]
+        assert sum(t["chosen"] for t in plans) == 1 and all(t["apply_ms"] > 0 for t in tune)
+        assert {t["streams"] for t in plans} == {1, 2}
+        assert {t["slab_order"] for t in plans} == {0, 1}
+        assert sorted(t["stencil_ty"] for t in tiles) == [4, 8, 16]
+        assert sum(t["chosen"] for t in tiles) == 1 and not any(t["cached"] for t in tune)
+        z1, y1 = h.new_vector(), h.new_vector()
         h.apply_precond(r, z1)
+        h.curlcurl_apply(r, y1)
         assert torch.equal(z0, z1), prec
+        assert torch.equal(y0, y1), prec
     h = api.Handle(doms[:1], device=DEV)
     with pytest.raises(api.FlashMPError, match="UNSUPPORTED"):
         h.autotune(r[:h.length].contiguous())
+
+
+def test_stencil_tile_heights_agree_bitwise():
+    """The 64 x 4, 64 x 8 and 64 x 16 stencil tiles compute the same y bit for bit
+    (each is made current in turn through the plan cache)."""
+    import os
+    import tempfile
+    nx, ny, nz = 70, 37, 21                          # ragged against every tile height
+    P = inputs.make_problem(dict(n=(nx, ny, nz), sub=0, c=2.0, eps_block=0, seed=9))
+    x = dev(P["rhs"])
+    ref = yee.apply_A_padded(P["rhs"], 2.0)
+    outs = []
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "plans.txt")
+        old = os.environ.get("FMP_TUNE_CACHE")
+        os.environ["FMP_TUNE_CACHE"] = path
+        try:
+            h = api.Handle([dict(nx=nx, ny=ny, nz=nz, c=2.0, sub=(0, 0, 0))], device=DEV,
+                           batch_boxes=-1)
+            tune = h.autotune(x, h.new_vector())
+            key, b, ns, so, ty = open(path).read().split()
+            for t in (4, 8, 16):                     # rewrite the record, re-tune from it
+                with open(path, "w") as f:
+                    f.write(f"{key} {b} {ns} {so} {t}\n")
+                hit = h.autotune(x, h.new_vector())
+                assert all(e["cached"] for e in hit)
+                assert [e["stencil_ty"] for e in hit if e["stencil_ty"]] == [t]
+                y = h.new_vector()
+                h.curlcurl_apply(x, y)
+                outs.append(host(y, ref.shape))
+            h.close()
+        finally:
+            if old is None:
+                del os.environ["FMP_TUNE_CACHE"]
+            else:
+                os.environ["FMP_TUNE_CACHE"] = old
+    assert any(e["chosen"] and e["stencil_ty"] for e in tune)
+    for o in outs:
+        assert np.array_equal(o, outs[0])
+        assert np.abs(o - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def test_autotune_plan_cache_round_trip():
+    """FMP_TUNE_CACHE: the first tuning appends a record, a second handle of the same
+    problem takes the recorded plan without timing the candidates."""
+    import os
+    import tempfile
+    spec = [(24, 12, 1.5), (16, 8, 0.5)]
+    doms = [dict(nx=n, ny=n, nz=n, c=c, sub=sub) for n, sub, c in spec]
+    rng = np.random.default_rng(5)
+    r = torch.cat([dev(inputs.normal_rhs(rng, n, n, n)) for n, _, _ in spec])
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "plans.txt")
+        old = os.environ.get("FMP_TUNE_CACHE")
+        os.environ["FMP_TUNE_CACHE"] = path
+        try:
+            h1 = api.Handle(doms, device=DEV, batch_boxes=-1)
+            t1 = h1.autotune(r, h1.new_vector())
+            assert not any(e["cached"] for e in t1) and len(open(path).readlines()) == 1
+            h2 = api.Handle(doms, device=DEV, batch_boxes=-1)
+            t2 = h2.autotune(r, h2.new_vector())
+            assert len(t2) == 2 and all(e["cached"] and e["chosen"] for e in t2)
+            pick = lambda t: sorted((e["batch_boxes"], e["streams"], e["slab_order"], e["stencil_ty"])
+                                    for e in t if e["chosen"])
+            assert pick(t1) == pick(t2)
+            z1, z2 = h1.new_vector(), h2.new_vector()
+            h1.apply_precond(r, z1)
+            h2.apply_precond(r, z2)
+            assert torch.equal(z1, z2)
+            # a different problem does not match the record
+            h3 = api.Handle(doms[:1], device=DEV, batch_boxes=-1)
+            t3 = h3.autotune(r[:h3.length].contiguous(), h3.new_vector())
+            assert not any(e["cached"] for e in t3) and len(open(path).readlines()) == 2
+        finally:
+            if old is None:
+                del os.environ["FMP_TUNE_CACHE"]
+            else:
+                os.environ["FMP_TUNE_CACHE"] = old
 
 
 @pytest.mark.slow

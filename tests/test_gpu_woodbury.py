@@ -165,3 +165,34 @@ def test_index_setup_errors():
         h.apply_precond(z.clone(), z)
     assert e.value.status == -6
     h.close()
+
+
+def test_index_blocks_of_several_domains():
+    """Two domains of different sizes, c and permittivity in one handle: each
+    domain's part of z equals the oracle's index-block RAS of that domain."""
+    rng = np.random.default_rng(21)
+    specs = [((12, 12, 12), (6, 6, 6), 2.0, 3, 0), ((10, 8, 6), (5, 4, 3), 5.0, 0, 0)]
+    doms, rs, refs = [], [], []
+    for (nx, ny, nz), sub, c, blk, _ in specs:
+        eps = inputs.eps_table(rng, nx, ny, nz, blk) if blk else None
+        eps_cell = yee.expand_eps(eps, blk, nx, ny, nz) if blk else None
+        r = inputs.normal_rhs(rng, nx, ny, nz)
+        doms.append(dict(nx=nx, ny=ny, nz=nz, c=c, eps=eps, eps_block=blk, sub=sub))
+        rs.append(r)
+        refs.append(woodbury.ras_apply_index(r, c, sub, 0, eps_cell))
+    for overlap in (0, 1):
+        if overlap:
+            refs = [woodbury.ras_apply_index(r, d["c"], d["sub"], 1,
+                                             yee.expand_eps(d["eps"], d["eps_block"], d["nx"],
+                                                            d["ny"], d["nz"])
+                                             if d["eps_block"] else None)
+                    for r, d in zip(rs, doms)]
+        h = api.Handle(doms, overlap=overlap, subdomain="index", device=DEV)
+        z = h.new_vector()
+        h.apply_precond(torch.cat([dev(r) for r in rs]), z)
+        torch.cuda.synchronize()
+        zz = z.cpu().numpy()
+        for d, ref in enumerate(refs):
+            a, b = h.offsets[d], h.offsets[d + 1]
+            assert relmax(zz[a:b].reshape(ref.shape), ref) <= TOL, (overlap, d)
+        h.close()
