@@ -29,6 +29,14 @@
 namespace fmp {
 namespace {
 
+// 1/d for d > 0 (a sum of four permittivities): hardware estimate, two Newton steps
+__device__ __forceinline__ double recip(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = __builtin_fma(__builtin_fma(-d, r, 1.0), r, r);
+  r = __builtin_fma(__builtin_fma(-d, r, 1.0), r, r);
+  return r;
+}
+
 constexpr int TX = kStencilTX;
 constexpr int HX = TX + 2;                // tile with halo in x
 
@@ -143,13 +151,16 @@ __global__ __launch_bounds__(TX * TY) void k_curlcurl(const double* __restrict__
     double sx = D.c, sy = D.c, sz = D.c;
     if (use_eps) {
       // edge permittivity: mean of the four cells sharing the edge, summed in
-      // the order (-,-), (+,-), (-,+), (+,+) of the two transverse axes
+      // the order (-,-), (+,-), (-,+), (+,+) of the two transverse axes;
+      // c / mean = 4c / sum, the reciprocal from the hardware estimate and
+      // two Newton steps (within an ulp or two of the division)
       const int em = (k + 1) & 1, e0 = k & 1;   // cell planes k-1 and k
       const int ja = ty + 1, ia = tx + 1;       // cell (j, i) inside the eps tile
-      sx = D.c / (0.25 * (((E[em][ja - 1][ia] + E[e0][ja - 1][ia]) + E[em][ja][ia]) + E[e0][ja][ia]));
-      sy = D.c / (0.25 * (((E[em][ja][ia - 1] + E[e0][ja][ia - 1]) + E[em][ja][ia]) + E[e0][ja][ia]));
-      sz = D.c / (0.25 * (((E[e0][ja - 1][ia - 1] + E[e0][ja][ia - 1]) + E[e0][ja - 1][ia]) +
-                          E[e0][ja][ia]));
+      const double c4 = 4.0 * D.c;
+      sx = c4 * recip(((E[em][ja - 1][ia] + E[e0][ja - 1][ia]) + E[em][ja][ia]) + E[e0][ja][ia]);
+      sy = c4 * recip(((E[em][ja][ia - 1] + E[e0][ja][ia - 1]) + E[em][ja][ia]) + E[e0][ja][ia]);
+      sz = c4 * recip(((E[e0][ja - 1][ia - 1] + E[e0][ja][ia - 1]) + E[e0][ja - 1][ia]) +
+                      E[e0][ja][ia]);
     }
     if (i < nx && j < ny) {                      // y is not re-read here: streaming stores
       const long long o = ((long long)k * ny + j) * nx + i;
