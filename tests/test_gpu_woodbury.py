@@ -196,3 +196,21 @@ def test_index_blocks_of_several_domains():
             a, b = h.offsets[d], h.offsets[d + 1]
             assert relmax(zz[a:b].reshape(ref.shape), ref) <= TOL, (overlap, d)
         h.close()
+
+
+def test_index_blocks_degenerate_c_zero():
+    """c = 0: A = I, the index-block RAS is the identity (no boundary correction is
+    formed); mixed with a domain of c > 0 in the same handle."""
+    rng = np.random.default_rng(8)
+    r0 = inputs.normal_rhs(rng, 8, 8, 8)
+    r1 = inputs.normal_rhs(rng, 8, 8, 8)
+    h = api.Handle([dict(nx=8, ny=8, nz=8, c=0.0, sub=4), dict(nx=8, ny=8, nz=8, c=2.0, sub=4)],
+                   overlap=0, subdomain="index", device=DEV)
+    z = h.new_vector()
+    h.apply_precond(torch.cat([dev(r0), dev(r1)]), z)
+    zz = host(z, (2,) + r0.shape)
+    h.close()
+    # the identity up to the rounding of the forward and inverse transforms
+    assert np.abs(zz[0] - r0).max() <= TOL * np.abs(r0).max()
+    ref1 = woodbury.ras_apply_index(r1, 2.0, (4, 4, 4), 0, None)
+    assert relmax(zz[1], ref1) <= TOL
