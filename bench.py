@@ -32,11 +32,15 @@ HBM_PEAK_GBS = 8000.0
 # since, traffic is null.
 TRAFFIC = {
     "k_mupdate": (1.0000, {"fmp_krylov.hip": "007a4daff79be785b7e7b45be9ae1a9a36d275d3d7dce1a34dbc36c12cb8fce5",
-                          "fmp_common.h": "33d0696ad75f124f9c64fd5b11a0246e476868a01db6b9078db1495178bab090"}),
-    "k_mdot": (1.0000, {"fmp_krylov.hip": "007a4daff79be785b7e7b45be9ae1a9a36d275d3d7dce1a34dbc36c12cb8fce5",
-                          "fmp_common.h": "33d0696ad75f124f9c64fd5b11a0246e476868a01db6b9078db1495178bab090"}),
-    "k_curlcurl": (1.0363, {"fmp_stencil.hip": "7fd7ff0c4eba81bdabfa8cbe6fb11d031c2ed4066c6f3f3a160de218c3ec3b12",
-                          "fmp_common.h": "33d0696ad75f124f9c64fd5b11a0246e476868a01db6b9078db1495178bab090"}),
+                          "fmp_common.h": "5fa9b1240eca9bf5a42db978f0e817d8130fd80be6ff88cb526515b09bef99ee"}),
+    "k_mdot": (1.0001, {"fmp_krylov.hip": "007a4daff79be785b7e7b45be9ae1a9a36d275d3d7dce1a34dbc36c12cb8fce5",
+                        "fmp_common.h": "5fa9b1240eca9bf5a42db978f0e817d8130fd80be6ff88cb526515b09bef99ee"}),
+    "k_curlcurl": (1.0266, {"fmp_stencil.hip": "306065c48e140d148793b0509d46e6541419178073c51d58105061fbdcfedec0",
+                            "fmp_common.h": "5fa9b1240eca9bf5a42db978f0e817d8130fd80be6ff88cb526515b09bef99ee"}),
+    # the three passes of one apply over the algorithmic 16 B per unknown
+    "precond_apply": (3.6155, {"fmp_transform.hip": "7f0c063e7d62874f22cf216585078251b116131491bc21d60a200d2ab50530a7",
+                               "fmp_api.hip": "e3e413621e3fbda0d70b724be93773eb9f5b89440f9dfc6070f7fec79cc01162",
+                               "fmp_common.h": "5fa9b1240eca9bf5a42db978f0e817d8130fd80be6ff88cb526515b09bef99ee"}),
 }
 
 
