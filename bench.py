@@ -38,8 +38,8 @@ TRAFFIC = {
     "k_curlcurl": (1.0266, {"fmp_stencil.hip": "306065c48e140d148793b0509d46e6541419178073c51d58105061fbdcfedec0",
                             "fmp_common.h": "5fa9b1240eca9bf5a42db978f0e817d8130fd80be6ff88cb526515b09bef99ee"}),
     # the three passes of one apply over the algorithmic 16 B per unknown
-    "precond_apply": (3.6155, {"fmp_transform.hip": "7f0c063e7d62874f22cf216585078251b116131491bc21d60a200d2ab50530a7",
-                               "fmp_api.hip": "e3e413621e3fbda0d70b724be93773eb9f5b89440f9dfc6070f7fec79cc01162",
+    "precond_apply": (3.5872, {"fmp_transform.hip": "e14b053ef8276fa1e721e10a2f64894049fc23adc0fb54bbf2e9b63a3632916b",
+                               "fmp_api.hip": "0dddaf4aeaf91c2a3568c0d78d8d9f4f23d45122452cb630cbaa56bf1143d8a5",
                                "fmp_common.h": "5fa9b1240eca9bf5a42db978f0e817d8130fd80be6ff88cb526515b09bef99ee"}),
 }
 

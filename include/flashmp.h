@@ -183,7 +183,9 @@ typedef struct {
  * the contractions as tiled GEMMs (FP64 / FP32) or matrix-core GEMMs (BF16);
  * 48 cells for index blocks) still gets a handle: the stencil and
  * unpreconditioned solves work, while fmp_apply_precond and preconditioned
- * solves return FMP_ERR_UNSUPPORTED. */
+ * solves return FMP_ERR_UNSUPPORTED.  BF16 handles refuse domains whose
+ * planes hold 2^27 cells or more (FMP_ERR_UNSUPPORTED): their gather
+ * addresses a slab of four planes by 32-bit byte offsets. */
 fmp_status fmp_setup_subdomains(const fmp_domain_desc* domains, int32_t n_domains,
                                 const fmp_precond_desc* pd, void* ws, size_t* ws_bytes,
                                 void* stream, fmp_handle* out);

@@ -410,6 +410,11 @@ fmp_status fmp_setup_subdomains(const fmp_domain_desc* domains, int32_t n_domain
     const fmp_domain_desc& D = domains[d];
     if (D.nx < 2 || D.ny < 2 || D.nz < 2 || !(D.c >= 0.0) || !isfinite(D.c))
       return FMP_ERR_INVALID_ARG;
+    if (h->prec == FMP_BF16 && 4LL * D.ny * D.nx >= (1LL << 29)) {
+      // the bf16 gather addresses a 4-plane slab by 32-bit byte offsets
+      h->err = "bf16 transforms need planes of fewer than 2^27 cells";
+      return FMP_ERR_UNSUPPORTED;
+    }
     const int sub[3] = {D.sub_x > 0 ? D.sub_x : D.nx, D.sub_y > 0 ? D.sub_y : D.ny,
                         D.sub_z > 0 ? D.sub_z : D.nz};
     const int nn[3] = {D.nx, D.ny, D.nz};

@@ -25,8 +25,9 @@
 //   A  gather 4 z-planes -> x GEMM -> y GEMM -> W (one chunk per lane and tile)
 //   B  z GEMM -> solve -> inverse z GEMM, W -> W
 //   C  W (one chunk per column) -> inverse y GEMM -> inverse x GEMM -> scatter
-// LDS operands are never zero-filled: fragment elements beyond the valid K
-// range, and rows beyond the valid range, are masked to zero as they are read.
+// The LDS buffers of passes A and C are zero-filled before they are staged,
+// so fragments read rows and K indices beyond the valid ranges as zeros
+// without masking; pass B masks its column fragments beyond nz.
 #include "fmp_common.h"
 
 namespace fmp {
@@ -111,19 +112,25 @@ __device__ __forceinline__ bf16x8 kmask(bf16x8 v, int k0, int n) {
   return __builtin_bit_cast(bf16x8, u);
 }
 
-// A fragments of this wave's NT row tiles (wave + 4 j) of an LDS operand;
-// rows for which ok(row) fails and K indices >= kn read as zero
-template <int NT, int KS, int RS, class OK>
-__device__ __forceinline__ void load_rows(bf16x8 (&a)[NT][KS], const __bf16* L, int wave, int l16,
-                                          int g, int kn, OK ok) {
+// A fragments of this wave's NT row tiles (wave + 4 j) of an LDS operand
+// whose padding (rows and K indices beyond the valid ranges) holds zeros
+template <int NT, int KS, int RS>
+__device__ __forceinline__ void load_rows_padded(bf16x8 (&a)[NT][KS], const __bf16* L, int wave,
+                                                 int l16, int g) {
 #pragma unroll
   for (int j = 0; j < NT; ++j) {
     const int row = (wave + 4 * j) * 16 + l16;
-    const bool rv = ok(row);
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks)
-      a[j][ks] = rv ? kmask(ld8(L + row * RS + 32 * ks + 8 * g), 32 * ks + 8 * g, kn) : zero8();
+    for (int ks = 0; ks < KS; ++ks) a[j][ks] = ld8(L + row * RS + 32 * ks + 8 * g);
   }
+}
+
+// zero n bf16 (a multiple of 8) of LDS with 16-byte stores
+template <int N>
+__device__ __forceinline__ void zero_lds(__bf16* L, int t) {
+  static_assert(N % 8 == 0, "whole 16-byte chunks");
+#pragma unroll
+  for (int i = t; i < N / 8; i += 256) *reinterpret_cast<bf16x8*>(L + 8 * i) = zero8();
 }
 
 // ---------------------------------------------------------------- pass A
@@ -133,7 +140,7 @@ __device__ __forceinline__ void load_rows(bf16x8 (&a)[NT][KS], const __bf16* L, 
 // owns the row tiles w, w + 4, ... (NT of them) in both GEMMs; table
 // fragments are loaded into registers once per block.
 template <int NP>
-__global__ __launch_bounds__(256) void k_mpass_a(const double* __restrict__ r, __bf16* __restrict__ W,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NP <= 34 ? 4 : 1))) void k_mpass_a(const double* __restrict__ r, __bf16* __restrict__ W,
                                                  const BoxDev* __restrict__ boxes,
                                                  const DomainDev* __restrict__ doms,
                                                  const int4* __restrict__ work,
@@ -152,11 +159,16 @@ __global__ __launch_bounds__(256) void k_mpass_a(const double* __restrict__ r, _
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int l16 = lane & 15, g = lane >> 4;
   bf16x8 tx[NT][KS], ty[NT][KS], a[NT][KS];
-  load_tab(tx, tb + (q == 0 ? B.mdct[0] : B.mdst[0]), l16, g);
+  // the slab's padding (rows beyond (nzs, ny), K beyond nx) and later the
+  // padding of Y (K beyond NR) must read as zero: fill the buffer first
+  zero_lds<ROWS * RS>(S, t);
+  __syncthreads();
 
   {  // S^gamma: the slab's nzs * ny * nx elements, walls as zero; loads first.
      // A thread's elements t + 256 i are stepped from its first one by the
-     // fixed increment of 256 elements (two carries), not decomposed anew.
+     // fixed increment of 256 elements (two carries), not decomposed anew;
+     // the LDS indices are stepped again when the values are committed, so
+     // that only the loaded values occupy registers while the loads fly.
     const int plane = ny * nx, tot = nzs * plane;
     const double* s0 = src + ((long long)(B.bz0 + z0) * D.ny + B.by0) * D.nx + B.bx0;
     int zl = t / plane, y = (t - zl * plane) / nx, x = t - zl * plane - y * nx;
@@ -166,6 +178,7 @@ __global__ __launch_bounds__(256) void k_mpass_a(const double* __restrict__ r, _
     const int doff = (dz * D.ny + dy) * D.nx + dx, dli = (dz * NR + dy) * RS + dx;
     const int cx_off = D.nx - nx, cx_li = RS - nx;               // x carry
     const int cy_off = (D.ny - ny) * D.nx, cy_li = (NR - ny) * RS; // y carry
+    const bool wx = q != 0, wy = q != 1, wz = q != 2;  // slot 0 of a node axis is a wall
     // elements in flight per thread: all of them up to 40, else chunks of 16
     constexpr int NI = (ZS * NP * NP + 255) / 256;
     constexpr int CH = NI <= 40 ? NI : 16;
@@ -173,30 +186,40 @@ __global__ __launch_bounds__(256) void k_mpass_a(const double* __restrict__ r, _
 #pragma unroll 1
     for (int ch = 0; ch < NCH; ++ch) {
       double v[CH];
-      int at[CH];
-      unsigned long long wall = 0;
+      const int x1 = x, y1 = y, z1 = zl, l1 = li;
 #pragma unroll
       for (int i = 0; i < CH; ++i) {
-        v[i] = s0[t + 256 * (ch * CH + i) < tot ? off : 0];
-        at[i] = li;
-        if (box_wall(q, x, y, z0 + zl)) wall |= 1ull << i;
-        x += dx; y += dy; zl += dz; off += doff; li += dli;
-        if (x >= nx) { x -= nx; ++y; off += cx_off; li += cx_li; }
-        if (y >= ny) { y -= ny; ++zl; off += cy_off; li += cy_li; }
+        // 32-bit byte offset from the slab's (uniform) base: one VGPR per
+        // address instead of two (setup refuses domains whose 4-plane span
+        // reaches 4 GiB)
+        const unsigned bo = (unsigned)(t + 256 * (ch * CH + i) < tot ? off : 0) * 8u;
+        v[i] = *reinterpret_cast<const double*>(reinterpret_cast<const char*>(s0) + bo);
+        x += dx; y += dy; off += doff;
+        if (x >= nx) { x -= nx; ++y; off += cx_off; }
+        if (y >= ny) { y -= ny; off += cy_off; }
       }
+      x = x1; y = y1; zl = z1; li = l1;
 #pragma unroll
-      for (int i = 0; i < CH; ++i)
-        if (t + 256 * (ch * CH + i) < tot) S[at[i]] = (__bf16)(((wall >> i) & 1ull) ? 0.0 : v[i]);
+      for (int i = 0; i < CH; ++i) {
+        // FP64 -> FP32 -> bf16, each step rounding to nearest even (the empty
+        // asm keeps the compiler from fusing the two into one exact rounding,
+        // which costs a dozen instructions per element)
+        float f = (float)v[i];
+        asm("" : "+v"(f));
+        const bool wall = (wx && x == 0) || (wy && y == 0) || (wz && z0 + zl == 0);
+        if (t + 256 * (ch * CH + i) < tot) S[li] = (__bf16)(wall ? 0.f : f);
+        x += dx; y += dy; zl += dz; li += dli;
+        if (x >= nx) { x -= nx; ++y; li += cx_li; }
+        if (y >= ny) { y -= ny; ++zl; li += cy_li; }
+      }
     }
   }
+  load_tab(tx, tb + (q == 0 ? B.mdct[0] : B.mdst[0]), l16, g);
   __syncthreads();
 
   // x: D[(zl, y)][p] = sum_x S[(zl, y)][x] T[p][x]
-  load_rows<NT, KS, RS>(a, S, wave, l16, g, nx,
-                        [&](int row) { return row % NR < ny && row / NR < nzs; });
+  load_rows_padded<NT, KS, RS>(a, S, wave, l16, g);
   __syncthreads();                                // S is overwritten by Y from here
-  constexpr bool kLarge = NP > 48;                // large classes hold one table at a time
-  if (!kLarge) load_tab(ty, tb + (q == 1 ? B.mdct[1] : B.mdst[1]), l16, g);
 #pragma unroll
   for (int j = 0; j < NT; ++j) {
     const int row = (wave + 4 * j) * 16 + 4 * g, zl = row / NR, y = row - zl * NR;
@@ -209,8 +232,8 @@ __global__ __launch_bounds__(256) void k_mpass_a(const double* __restrict__ r, _
   __syncthreads();
 
   // y: D[(p, zl)][q'] = sum_y Y[(p, zl)][y] T[q'][y]  ->  chunk z0 / 4 of column (p, q')
-  if (kLarge) load_tab(ty, tb + (q == 1 ? B.mdct[1] : B.mdst[1]), l16, g);
-  load_rows<NT, KS, RS>(a, S, wave, l16, g, ny, [](int) { return true; });
+  load_tab(ty, tb + (q == 1 ? B.mdct[1] : B.mdst[1]), l16, g);   // one table live at a time
+  load_rows_padded<NT, KS, RS>(a, S, wave, l16, g);
   __bf16* Wc = W + B.w_off + (long long)q * box_wvol(B, true) + (long long)(z0 / 4) * ny * nx * 4;
 #pragma unroll
   for (int j = 0; j < NT; ++j) {
@@ -350,9 +373,10 @@ __global__ __launch_bounds__(256) void k_mpass_c(const __bf16* __restrict__ W, d
   const int lx0 = B.ox0 - B.bx0, lx1 = lx0 + B.sx;
   if (z0 + ZS <= lz0 || z0 >= lz1) return;         // no owned plane in this slab
   bf16x8 ty[NT][KS], tx[NT][KS], a[NT][KS];
-  constexpr bool kLarge = NP > 48;                // large classes hold one table at a time
-  load_tab(ty, tb + (q == 1 ? B.mdctT[1] : B.mdst[1]), l16, g);
-  if (!kLarge) load_tab(tx, tb + (q == 0 ? B.mdctT[0] : B.mdst[0]), l16, g);
+  // rows p >= nx and K indices beyond ny of X, and K beyond NR of U, must
+  // read as zero: fill the buffer first
+  zero_lds<ROWS * RS>(X, t);
+  __syncthreads();
 
   {  // chunk z0 / 4 of the slab's columns (p, q'): X[(p, zl)][q'], two
      // neighbouring columns (q', q'+1) per step: one 16-byte read of W and
@@ -372,10 +396,11 @@ __global__ __launch_bounds__(256) void k_mpass_c(const __bf16* __restrict__ W, d
       }
     }
   }
+  load_tab(ty, tb + (q == 1 ? B.mdctT[1] : B.mdst[1]), l16, g);
   __syncthreads();
 
   // inverse y: D[(p, zl)][m] = sum_q' X[(p, zl)][q'] Ti[m][q']; rows p >= nx read as zero
-  load_rows<NT, KS, RS>(a, X, wave, l16, g, ny, [&](int row) { return row / ZS < nx; });
+  load_rows_padded<NT, KS, RS>(a, X, wave, l16, g);
   __syncthreads();                                // X is overwritten by U from here
 #pragma unroll
   for (int j = 0; j < NT; ++j) {
@@ -391,8 +416,8 @@ __global__ __launch_bounds__(256) void k_mpass_c(const __bf16* __restrict__ W, d
   __syncthreads();
 
   // inverse x: D[(y, zl)][l] = sum_p U[(y, zl)][p] Ti[l][p], then S^0T
-  if (kLarge) load_tab(tx, tb + (q == 0 ? B.mdctT[0] : B.mdst[0]), l16, g);
-  load_rows<NT, KS, RS>(a, X, wave, l16, g, nx, [](int) { return true; });
+  load_tab(tx, tb + (q == 0 ? B.mdctT[0] : B.mdst[0]), l16, g);
+  load_rows_padded<NT, KS, RS>(a, X, wave, l16, g);
   const DomainDev& D = doms[B.dom];
   double* dst = z + D.offset + (long long)q * D.nz * D.ny * D.nx;
   const double cq = coarse ? coarse[(long long)q * nsub + B.sub] : 0.0;

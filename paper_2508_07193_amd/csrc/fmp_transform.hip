@@ -197,6 +197,69 @@ __device__ __forceinline__ void inv_bfly(const T* __restrict__ tab, const Half g
   if (g.base) st(0, T(0));                        // DST-I: the wall slot
 }
 
+// Split forms for workgroups in which two threads share each pencil.  The
+// pencil is read in full by both (bfly_sums_or_diffs, inv_load), every thread
+// of the workgroup passes a barrier, then each thread computes half of the
+// outputs: the forward splits by parity (part 0 the sums' rows, i.e. the
+// outputs base + 2k, part 1 the differences' rows), the inverse by output
+// pairs (part 0 the pairs j < (P + 1) / 2, part 1 the rest and the middle
+// index).  Every output is the same row product as in fwd_bfly / inv_bfly,
+// summed in the same order, so the results are bitwise those of the
+// unsplit forms.
+template <typename T, int NH, class Load>
+__device__ __forceinline__ void bfly_sums_or_diffs(const Half g, int part, Load ld, T (&u)[NH]) {
+#pragma unroll
+  for (int j = 0; j < NH; ++j) {
+    T xa = T(0), xb = T(0);
+    if (j < g.P) {
+      xa = ld(g.base + j);
+      xb = ld(g.n - 1 - j);
+    } else if (j == g.P && g.mid) {
+      xa = ld(g.c);
+    }
+    u[j] = part == 0 ? xa + xb : xa - xb;
+  }
+}
+
+template <typename T, int NH, class Store>
+__device__ __forceinline__ void fwd_part(const T* __restrict__ tab, const Half g, int part,
+                                         const T (&u)[NH], Store st) {
+  if (part == 0) {
+    rows_times<T, NH>(tab, g.P + g.mid, u, [&](int k, T val) { st(g.base + 2 * k, val); });
+    if (g.base) st(0, T(0));                      // DST-I: slot 0 holds no mode
+  } else {
+    rows_times<T, NH>(tab + kHS * kHS, g.P, u, [&](int k, T val) { st(g.base + 2 * k + 1, val); });
+  }
+}
+
+template <typename T, int NH, class Load>
+__device__ __forceinline__ void inv_load(const Half g, Load ld, T (&ys)[NH], T (&yd)[NH]) {
+  const int NS = g.P + g.mid;
+#pragma unroll
+  for (int k = 0; k < NH; ++k) {
+    ys[k] = (k < NS) ? ld(g.base + 2 * k) : T(0);
+    yd[k] = (k < g.P) ? ld(g.base + 2 * k + 1) : T(0);
+  }
+}
+
+template <typename T, int NH, class Store>
+__device__ __forceinline__ void inv_part(const T* __restrict__ tab, const Half g, int part,
+                                         const T (&ys)[NH], const T (&yd)[NH], Store st) {
+  const T* __restrict__ TSt = tab + 2 * kHS * kHS;
+  const T* __restrict__ TDt = tab + 3 * kHS * kHS;
+  const int jm = (g.P + 1) >> 1;
+  const int j0 = part == 0 ? 0 : jm, j1 = part == 0 ? jm : g.P;
+#pragma unroll 1
+  for (int j = j0; j < j1; ++j) {
+    T e, o;
+    row_dot2<T, NH>(TSt + j * kHS, TDt + j * kHS, ys, yd, e, o);
+    st(g.base + j, e + o);
+    st(g.n - 1 - j, e - o);
+  }
+  if (part == 1 && g.mid) st(g.c, row_dot<T, NH>(TSt + g.P * kHS, ys));
+  if (part == 0 && g.base) st(0, T(0));           // DST-I: the wall slot
+}
+
 template <typename T>
 __device__ __forceinline__ T recip(T d) {
   return T(1) / d;
@@ -216,9 +279,13 @@ __device__ __forceinline__ bool box_wall(int q, int x, int y, int z) {
 }
 
 
-// Passes A and C run 128-thread workgroups over slabs of 128/NP planes: the
-// FP64 slab then needs ~28 KB of LDS (5 workgroups per CU instead of 2 with
-// 256 threads), which is what hides the gather latency.
+// Passes A and C work on slabs of kAC/NP planes (kAC pencils per direction):
+// the FP64 slab then needs ~28 KB of LDS, 5 workgroups per CU.  The
+// workgroups have 2 kAC threads, two per pencil (each forms half of the
+// pencil's outputs), which doubles the waves per CU at the same LDS: at the
+// 512 boxes of 34^3 of a 256^3 grid, FP64 pass A 347 -> 273 us and pass C
+// 319 -> 274 us, FP32 pass A 216 -> 186 us.  FP32 pass C keeps one thread
+// per pencil (its split form needs 104 VGPRs: 232 us against 177 us).
 constexpr int kAC = 128;
 template <int NP>
 constexpr int zslab() {
@@ -231,15 +298,17 @@ constexpr int zslab() {
 // selected afterwards): the kernels are latency-bound otherwise.
 
 // ---------------------------------------------------------------- pass A
-template <typename T, int NP>
-__global__ __launch_bounds__(kAC) void k_pass_a(const double* __restrict__ r, T* __restrict__ W,
+template <typename T, int NP, int NTH>
+__global__ __launch_bounds__(NTH) void k_pass_a(const double* __restrict__ r, T* __restrict__ W,
                                                 const BoxDev* __restrict__ boxes,
                                                 const DomainDev* __restrict__ doms,
                                                 const int4* __restrict__ work,
                                                 const T* __restrict__ tab) {
+  static_assert(NTH == kAC || NTH == 2 * kAC, "one or two threads per pencil");
   constexpr int ZS = zslab<NP>();
-  constexpr int MAXE = (ZS * NP * NP + kAC - 1) / kAC;
+  constexpr int MAXE = (ZS * NP * NP + NTH - 1) / NTH;
   constexpr int NH = NP / 2;
+  static_assert(MAXE <= 64, "wall flags are kept in one 64-bit mask");
   __shared__ T buf[ZS * NP * NP];
   const int4 wk = work[xcd_remap(blockIdx.x, gridDim.x)];
   const BoxDev& B = boxes[wk.x];
@@ -252,13 +321,12 @@ __global__ __launch_bounds__(kAC) void k_pass_a(const double* __restrict__ r, T*
   const int tot = nzs * plane;
   const int t = threadIdx.x;
 
-  static_assert(MAXE <= 64, "wall flags are kept in one 64-bit mask");
-  // S^gamma: gather the slab.  A thread's elements t + kAC i are stepped from
-  // its first one by the fixed increment of kAC elements (two carries), with
+  // S^gamma: gather the slab.  A thread's elements t + NTH i are stepped from
+  // its first one by the fixed increment of NTH elements (two carries), with
   // no per-element division; loads of out-of-slab steps read element 0.
   const double* s0 = src + ((long long)(B.bz0 + z0) * D.ny + B.by0) * D.nx + B.bx0;
   int zl = t / plane, y = (t - zl * plane) / nx, x = t - zl * plane - y * nx;
-  const int dz = kAC / plane, rk = kAC - dz * plane, dy = rk / nx, dx = rk - dy * nx;
+  const int dz = NTH / plane, rk = NTH - dz * plane, dy = rk / nx, dx = rk - dy * nx;
   int off = (zl * D.ny + y) * D.nx + x;
   const int doff = (dz * D.ny + dy) * D.nx + dx;
   const int cx_off = D.nx - nx, cy_off = (D.ny - ny) * D.nx;
@@ -266,7 +334,7 @@ __global__ __launch_bounds__(kAC) void k_pass_a(const double* __restrict__ r, T*
   unsigned long long wall = 0;
 #pragma unroll
   for (int i = 0; i < MAXE; ++i) {
-    vals[i] = s0[t + kAC * i < tot ? off : 0];
+    vals[i] = s0[t + NTH * i < tot ? off : 0];
     if (box_wall(q, x, y, z0 + zl)) wall |= 1ull << i;
     x += dx; y += dy; zl += dz; off += doff;
     if (x >= nx) { x -= nx; ++y; off += cx_off; }
@@ -274,23 +342,45 @@ __global__ __launch_bounds__(kAC) void k_pass_a(const double* __restrict__ r, T*
   }
 #pragma unroll
   for (int i = 0; i < MAXE; ++i) {
-    const int e = t + kAC * i;
+    const int e = t + NTH * i;
     if (e < tot) buf[e] = ((wall >> i) & 1ull) ? T(0) : (T)vals[i];
   }
   __syncthreads();
 
-  if (t < nzs * ny) {                             // x, one row per lane (in place)
-    T* row = buf + t * nx;
-    fwd_bfly<T, NH>(tab + B.half[0][q == 0 ? 0 : 1], half_geom(nx, q == 0 ? 0 : 1),
-                    [&](int l) { return row[l]; }, [&](int p, T v) { row[p] = v; });
-  }
-  __syncthreads();
-  if (t < nzs * nx) {                             // y, one column per lane, to the staging
-    const int zl = t / nx, x = t - zl * nx;
-    const T* colp = buf + zl * plane + x;
-    T* dst = W + B.w_off + (long long)q * B.vol + (long long)(z0 + zl) * plane + x;
-    fwd_bfly<T, NH>(tab + B.half[1][q == 1 ? 0 : 1], half_geom(ny, q == 1 ? 0 : 1),
-                    [&](int m) { return colp[m * nx]; }, [&](int p, T v) { dst[p * nx] = v; });
+  const T* tabx = tab + B.half[0][q == 0 ? 0 : 1];
+  const T* taby = tab + B.half[1][q == 1 ? 0 : 1];
+  const Half gx = half_geom(nx, q == 0 ? 0 : 1), gy = half_geom(ny, q == 1 ? 0 : 1);
+  T* dst0 = W + B.w_off + (long long)q * B.vol + (long long)z0 * plane;
+  if constexpr (NTH == kAC) {
+    if (t < nzs * ny) {                           // x, one row per lane (in place)
+      T* row = buf + t * nx;
+      fwd_bfly<T, NH>(tabx, gx, [&](int l) { return row[l]; }, [&](int p, T v) { row[p] = v; });
+    }
+    __syncthreads();
+    if (t < nzs * nx) {                           // y, one column per lane, to the staging
+      const int zl = t / nx, x = t - zl * nx;
+      const T* colp = buf + zl * plane + x;
+      T* dst = dst0 + zl * plane + x;
+      fwd_bfly<T, NH>(taby, gy, [&](int m) { return colp[m * nx]; },
+                      [&](int p, T v) { dst[p * nx] = v; });
+    }
+  } else {
+    // two threads per pencil: waves 0-1 form the even outputs, waves 2-3 the odd ones
+    const int part = __builtin_amdgcn_readfirstlane(t / kAC);
+    const int u = t - part * kAC;
+    T hv[NH];
+    T* row = buf + u * nx;
+    if (u < nzs * ny) bfly_sums_or_diffs<T, NH>(gx, part, [&](int l) { return row[l]; }, hv);
+    __syncthreads();                              // the row is overwritten in place
+    if (u < nzs * ny) fwd_part<T, NH>(tabx, gx, part, hv, [&](int p, T v) { row[p] = v; });
+    __syncthreads();
+    if (u < nzs * nx) {
+      const int zl = u / nx, x = u - zl * nx;
+      const T* colp = buf + zl * plane + x;
+      T* dst = dst0 + zl * plane + x;
+      bfly_sums_or_diffs<T, NH>(gy, part, [&](int m) { return colp[m * nx]; }, hv);
+      fwd_part<T, NH>(taby, gy, part, hv, [&](int p, T v) { dst[p * nx] = v; });
+    }
   }
 }
 
@@ -540,15 +630,16 @@ __global__ __launch_bounds__(192) void k_pass_b_ring(T* __restrict__ W,
 }
 
 // ---------------------------------------------------------------- pass C
-template <typename T, int NP>
-__global__ __launch_bounds__(kAC) void k_pass_c(const T* __restrict__ W, double* __restrict__ z,
+template <typename T, int NP, int NTH>
+__global__ __launch_bounds__(NTH) void k_pass_c(const T* __restrict__ W, double* __restrict__ z,
                                                 const BoxDev* __restrict__ boxes,
                                                 const DomainDev* __restrict__ doms,
                                                 const int4* __restrict__ work,
                                                 const T* __restrict__ tab,
                                                 const double* __restrict__ coarse, int nsub) {
+  static_assert(NTH == kAC || NTH == 2 * kAC, "one or two threads per pencil");
   constexpr int ZS = zslab<NP>();
-  constexpr int MAXE = (ZS * NP * NP + kAC - 1) / kAC;
+  constexpr int MAXE = (ZS * NP * NP + NTH - 1) / NTH;
   constexpr int NH = NP / 2;
   __shared__ T buf[ZS * NP * NP];
   const int4 wk = work[xcd_remap(blockIdx.x, gridDim.x)];
@@ -559,51 +650,75 @@ __global__ __launch_bounds__(kAC) void k_pass_c(const T* __restrict__ W, double*
   const int plane = ny * nx;
   const int tot = nzs * plane;
   const int t = threadIdx.x;
+  const int lz0 = max(z0, B.oz0 - B.bz0), lz1 = min(z0 + nzs, B.oz0 - B.bz0 + B.sz);
+  if (lz1 <= lz0) return;                         // no owned plane in this slab
   const T* srcw = W + B.w_off + (long long)q * B.vol + (long long)z0 * plane;
 
   T vals[MAXE];                                   // the staged slab is contiguous
 #pragma unroll
-  for (int i = 0; i < MAXE; ++i) vals[i] = srcw[min(t + kAC * i, tot - 1)];
+  for (int i = 0; i < MAXE; ++i) vals[i] = srcw[min(t + NTH * i, tot - 1)];
 #pragma unroll
   for (int i = 0; i < MAXE; ++i)
-    if (t + kAC * i < tot) buf[t + kAC * i] = vals[i];
+    if (t + NTH * i < tot) buf[t + NTH * i] = vals[i];
   __syncthreads();
 
-  if (t < nzs * nx) {                             // y inverse, one column per lane (in place)
-    const int zl = t / nx, x = t - zl * nx;
-    T* colp = buf + zl * plane + x;
-    inv_bfly<T, NH>(tab + B.half[1][q == 1 ? 0 : 1], half_geom(ny, q == 1 ? 0 : 1),
-                    [&](int m) { return colp[m * nx]; }, [&](int m, T v) { colp[m * nx] = v; });
-  }
-  __syncthreads();
-  if (t < nzs * ny) {                             // x inverse, one row per lane (in place)
-    T* row = buf + t * nx;
-    inv_bfly<T, NH>(tab + B.half[0][q == 0 ? 0 : 1], half_geom(nx, q == 0 ? 0 : 1),
-                    [&](int p) { return row[p]; }, [&](int l, T v) { row[l] = v; });
+  const T* taby = tab + B.half[1][q == 1 ? 0 : 1];
+  const T* tabx = tab + B.half[0][q == 0 ? 0 : 1];
+  const Half gy = half_geom(ny, q == 1 ? 0 : 1), gx = half_geom(nx, q == 0 ? 0 : 1);
+  if constexpr (NTH == kAC) {
+    if (t < nzs * nx) {                           // y inverse, one column per lane (in place)
+      const int zl = t / nx, x = t - zl * nx;
+      T* colp = buf + zl * plane + x;
+      inv_bfly<T, NH>(taby, gy, [&](int m) { return colp[m * nx]; },
+                      [&](int m, T v) { colp[m * nx] = v; });
+    }
+    __syncthreads();
+    if (t < nzs * ny) {                           // x inverse, one row per lane (in place)
+      T* row = buf + t * nx;
+      inv_bfly<T, NH>(tabx, gx, [&](int p) { return row[p]; }, [&](int l, T v) { row[l] = v; });
+    }
+  } else {
+    // two threads per pencil: waves 0-1 form the outputs of the first half of
+    // the butterfly pairs, waves 2-3 the rest; each pencil is read in full by
+    // both before either overwrites it
+    const int part = __builtin_amdgcn_readfirstlane(t / kAC);
+    const int u = t - part * kAC;
+    T ys[NH], yd[NH];
+    {
+      const int zl = u / nx, x = u - zl * nx;
+      T* colp = buf + zl * plane + x;
+      if (u < nzs * nx) inv_load<T, NH>(gy, [&](int m) { return colp[m * nx]; }, ys, yd);
+      __syncthreads();
+      if (u < nzs * nx)
+        inv_part<T, NH>(taby, gy, part, ys, yd, [&](int m, T v) { colp[m * nx] = v; });
+    }
+    __syncthreads();
+    T* row = buf + u * nx;
+    if (u < nzs * ny) inv_load<T, NH>(gx, [&](int p) { return row[p]; }, ys, yd);
+    __syncthreads();
+    if (u < nzs * ny) inv_part<T, NH>(tabx, gx, part, ys, yd, [&](int l, T v) { row[l] = v; });
   }
   __syncthreads();
 
   // S^0T: write the owned part of the slab
-  const int lz0 = max(z0, B.oz0 - B.bz0), lz1 = min(z0 + nzs, B.oz0 - B.bz0 + B.sz);
-  if (lz1 <= lz0) return;
   const int ly0 = B.oy0 - B.by0, lx0 = B.ox0 - B.bx0;
   const int oplane = B.sy * B.sx;
   const int otot = (lz1 - lz0) * oplane;
   const DomainDev& D = doms[B.dom];
   double* dst = z + D.offset + (long long)q * D.nz * D.ny * D.nx;
   const double cq = coarse ? coarse[(long long)q * nsub + B.sub] : 0.0;
-  // owned element t + kAC i: (zl, y, x) stepped by the fixed increment of kAC
+  // owned element t + NTH i: (zl, y, x) stepped by the fixed increment of NTH
   // (two carries) with its slab index and its place in z
   const int sx = B.sx, sy = B.sy;
   int zl = t / oplane, y = (t - zl * oplane) / sx, x = t - zl * oplane - y * sx;
-  const int dz = kAC / oplane, rk = kAC - dz * oplane, dy = rk / sx, dx = rk - dy * sx;
+  const int dz = NTH / oplane, rk = NTH - dz * oplane, dy = rk / sx, dx = rk - dy * sx;
   int bi = (lz0 + zl - z0) * plane + (ly0 + y) * nx + lx0 + x;
   long long go = ((long long)(B.bz0 + lz0 + zl) * D.ny + (B.by0 + ly0 + y)) * D.nx + B.bx0 + lx0 + x;
   const int dbi = dz * plane + dy * nx + dx;
   const long long dgo = ((long long)dz * D.ny + dy) * D.nx + dx;
   const int cx_bi = nx - sx, cy_bi = plane - sy * nx;
   const long long cx_go = D.nx - sx, cy_go = (long long)(D.ny - sy) * D.nx;
-  for (int e = t; e < otot; e += kAC) {
+  for (int e = t; e < otot; e += NTH) {
     double val = (double)buf[bi];
     if (coarse && !box_wall(q, B.bx0 + lx0 + x, B.by0 + ly0 + y, B.bz0 + lz0 + zl)) val += cq;
     dst[go] = val;
@@ -613,11 +728,19 @@ __global__ __launch_bounds__(kAC) void k_pass_c(const T* __restrict__ W, double*
   }
 }
 
+// threads per workgroup of passes A and C: two per pencil, except in the
+// FP32 pass C
+template <typename T>
+constexpr int kThreadsA = 2 * kAC;
+template <typename T>
+constexpr int kThreadsC = sizeof(T) == 8 ? 2 * kAC : kAC;
+
 template <typename T, int NP>
 hipError_t run_a(const double* r, void* W, const BoxDev* boxes, const DomainDev* doms,
                  const int4* work, int nwork, const void* tab, hipStream_t s) {
-  hipLaunchKernelGGL((k_pass_a<T, NP>), dim3(nwork), dim3(kAC), 0, s, r, (T*)W, boxes, doms, work,
-                     (const T*)tab);
+  constexpr int NTH = kThreadsA<T>;
+  hipLaunchKernelGGL((k_pass_a<T, NP, NTH>), dim3(nwork), dim3(NTH), 0, s, r, (T*)W, boxes, doms,
+                     work, (const T*)tab);
   return hipGetLastError();
 }
 template <typename T, int NP>
@@ -635,8 +758,9 @@ template <typename T, int NP>
 hipError_t run_c(const void* W, double* z, const BoxDev* boxes, const DomainDev* doms,
                  const int4* work, int nwork, const void* tab, const double* coarse, int nsub,
                  hipStream_t s) {
-  hipLaunchKernelGGL((k_pass_c<T, NP>), dim3(nwork), dim3(kAC), 0, s, (const T*)W, z, boxes, doms,
-                     work, (const T*)tab, coarse, nsub);
+  constexpr int NTH = kThreadsC<T>;
+  hipLaunchKernelGGL((k_pass_c<T, NP, NTH>), dim3(nwork), dim3(NTH), 0, s, (const T*)W, z, boxes,
+                     doms, work, (const T*)tab, coarse, nsub);
   return hipGetLastError();
 }
 

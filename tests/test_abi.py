@@ -137,3 +137,18 @@ def test_ctypes_structs_match_the_c_layout(tmp_path):
         assert got[(cname, "size")] == C.sizeof(py), cname
         for fname, _ in py._fields_:
             assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
+
+
+def test_bf16_refuses_planes_beyond_its_32bit_slab_offsets(L):
+    # the bf16 gather addresses a 4-plane slab by 32-bit byte offsets:
+    # planes of 2^27 cells or more are refused at setup, in bf16 only
+    def flat(nx, ny):
+        d = _desc(n=2, sub=0)
+        d.nx, d.ny = nx, ny
+        return d
+    st, _ = _size(L, [flat(16384, 8192)], prec=2)        # 2^27 cells per plane
+    assert st == -6
+    st, _ = _size(L, [flat(16384, 8192)], prec=0)
+    assert st == 0
+    st, _ = _size(L, [flat(8192, 8192)], prec=2)         # 2^26: within range
+    assert st == 0
