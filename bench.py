@@ -35,10 +35,11 @@ TRAFFIC = {
                           "fmp_common.h": "5fa9b1240eca9bf5a42db978f0e817d8130fd80be6ff88cb526515b09bef99ee"}),
     "k_mdot": (1.0001, {"fmp_krylov.hip": "007a4daff79be785b7e7b45be9ae1a9a36d275d3d7dce1a34dbc36c12cb8fce5",
                         "fmp_common.h": "5fa9b1240eca9bf5a42db978f0e817d8130fd80be6ff88cb526515b09bef99ee"}),
-    "k_curlcurl": (1.0266, {"fmp_stencil.hip": "306065c48e140d148793b0509d46e6541419178073c51d58105061fbdcfedec0",
+    # per stencil tile height (halo rows re-read through L2 differ by tile)
+    "k_curlcurl": ({4: 1.0412, 8: 1.0357, 16: 1.0245}, {"fmp_stencil.hip": "696e04ec48a51593d192077df34e99a631009e7660df29edde94fb7fbba8ea32",
                             "fmp_common.h": "5fa9b1240eca9bf5a42db978f0e817d8130fd80be6ff88cb526515b09bef99ee"}),
     # the three passes of one apply over the algorithmic 16 B per unknown
-    "precond_apply": (3.5872, {"fmp_transform.hip": "e14b053ef8276fa1e721e10a2f64894049fc23adc0fb54bbf2e9b63a3632916b",
+    "precond_apply": (3.5879, {"fmp_transform.hip": "088abf9b8896e3e557464f37e6c273226e17e0e0e5c5cb55a9815bd5ca2b3932",
                                "fmp_api.hip": "0dddaf4aeaf91c2a3568c0d78d8d9f4f23d45122452cb630cbaa56bf1143d8a5",
                                "fmp_common.h": "5fa9b1240eca9bf5a42db978f0e817d8130fd80be6ff88cb526515b09bef99ee"}),
 }
@@ -67,11 +68,15 @@ def transform_flops_per_apply(n, sub, overlap=1):
     return 2.0 * fma
 
 
-def traffic_ratio(name):
+def traffic_ratio(name, variant=None):
     import hashlib
     if name not in TRAFFIC:
         return None
     ratio, srcs = TRAFFIC[name]
+    if isinstance(ratio, dict):
+        ratio = ratio.get(variant)
+        if ratio is None:
+            return None
     d = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2508_07193_amd", "csrc")
     for f, h in srcs.items():
         try:
@@ -594,10 +599,11 @@ def c3_context(args):
         hh = api.Handle([dom], overlap=1, precision=prec, device=dev, batch_boxes=-1,
                         use_graph=args.graphs)
         t = hh.autotune(b)
-        c = [e for e in t if e["chosen"]][0]
-        log(f"[{prec}] autotune: {[(e['batch_boxes'], e['streams'], e['slab_order'], round(e['apply_ms'], 4)) for e in t]}")
+        c = [e for e in t if e["chosen"] and not e["stencil_ty"]][0]
+        ty = [e["stencil_ty"] for e in t if e["chosen"] and e["stencil_ty"]]
+        log(f"[{prec}] autotune: {[(e['batch_boxes'], e['streams'], e['slab_order'], e['stencil_ty'], round(e['apply_ms'], 4)) for e in t]}")
         return hh, dict(batch_boxes=c["batch_boxes"], streams=c["streams"], slab_order=c["slab_order"],
-                        graph=bool(args.graphs))
+                        graph=bool(args.graphs), stencil_ty=ty[0] if ty else None)
 
     return dict(torch=torch, P=P, b=b, n_unk=n_unk, run_solves=run_solves,
                 time_events=time_events, tuned_handle=tuned_handle)
@@ -616,9 +622,9 @@ def main_leg(args):
     t_pre = time_events(lambda: h.apply_precond(b, z), 10)
     t_spmv = time_events(lambda: h.curlcurl_apply(b, y), 20)
 
-    def roof(name, kernel, bytes_per_launch, avg_ms, per):
+    def roof(name, kernel, bytes_per_launch, avg_ms, per, variant=None):
         ach = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-        ratio = traffic_ratio(name)
+        ratio = traffic_ratio(name, variant)
         return dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(ach / HBM_PEAK_GBS, 3),
                     traffic=None if ratio is None else round(ratio * bytes_per_launch),
@@ -640,8 +646,9 @@ def main_leg(args):
                        pinfo["bytes_orth_dot"] / pinfo["n_orth_dot"],
                        pinfo["t_orth_dot_ms"] / pinfo["n_orth_dot"],
                        "8 B x len x (j+2) per launch (reads V_0..V_j and w)"),
-        "k_curlcurl": roof("k_curlcurl", "k_curlcurl (stencil y = A x)", spmv_bytes, t_spmv,
-                           "16 B per unknown (x in, y out)"),
+        "k_curlcurl": roof("k_curlcurl", f"k_curlcurl (stencil y = A x, 64 x {plan64['stencil_ty']} tiles)",
+                           spmv_bytes, t_spmv, "16 B per unknown (x in, y out)",
+                           variant=plan64["stencil_ty"]),
         "precond_apply": roof("precond_apply", "precond apply (passes A, B, C)", 16.0 * n_unk, t_pre,
                               "16 B per unknown (r in, z out); staging traffic excluded"),
     }

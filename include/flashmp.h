@@ -65,7 +65,8 @@ typedef enum { FMP_FP64 = 0, FMP_FP32 = 1, FMP_BF16 = 2 } fmp_precision;
 /* One domain: a box of nx*ny*nz unit cells with PEC walls on all six faces.
  * c = dt^2/(4 mu eps0 h^2) (the alpha of eq. (7) for eps_r = 1).
  * eps_block: host array of relative permittivities, one per cube of
- *   eps_block_size^3 cells, C order [nz/b][ny/b][nx/b]; NULL means eps_r = 1.
+ *   eps_block_size^3 cells, C order [ceil(nz/b)][ceil(ny/b)][ceil(nx/b)]
+ *   (the library reads that many values); NULL means eps_r = 1.
  *   The permittivity at an E edge is the mean over the four cells sharing it.
  * sub_x/y/z: owned subdomain side in cells (must divide the domain side;
  *   0 = the whole axis, i.e. one box). */

@@ -44,7 +44,8 @@ def _check(st, where, h=None, ok=(0,)):
 
 
 def domain_desc(nx, ny, nz, c, eps=None, eps_block=0, sub=(0, 0, 0)):
-    """Build an fmp_domain_desc; `eps` is the (nz/b, ny/b, nx/b) permittivity table or None."""
+    """Build an fmp_domain_desc; `eps` is the (ceil(nz/b), ceil(ny/b), ceil(nx/b))
+    permittivity table or None."""
     d = _lib.DomainDesc()
     d.nx, d.ny, d.nz, d.c = int(nx), int(ny), int(nz), float(c)
     sub = (sub, sub, sub) if np.isscalar(sub) else tuple(sub)
@@ -52,6 +53,11 @@ def domain_desc(nx, ny, nz, c, eps=None, eps_block=0, sub=(0, 0, 0)):
     keep = None
     if eps is not None:
         keep = np.ascontiguousarray(eps, dtype=np.float64)
+        b = int(eps_block)
+        want = tuple(-(-int(n) // b) for n in (nz, ny, nx)) if b > 0 else None
+        if want is None or keep.shape != want:
+            raise ValueError(f"eps table of shape {keep.shape} for a {nx}x{ny}x{nz} domain "
+                             f"with eps_block={eps_block}: expected {want}")
         d.eps_block = keep.ctypes.data_as(C.POINTER(C.c_double))
         d.eps_block_size = int(eps_block)
     else:

@@ -95,8 +95,8 @@ struct fmp_ctx {
   long long len = 0;
   int ntiles = 0;                      // stencil tiles of the chosen tile height
   int stencil_v = fmp::kStencilDefault;
-  int ntiles_v[fmp::kNumStencilTY] = {0, 0, 0};
-  StencilTile* d_tiles_v[fmp::kNumStencilTY] = {nullptr, nullptr, nullptr};
+  int ntiles_v[fmp::kNumStencilTY] = {};
+  StencilTile* d_tiles_v[fmp::kNumStencilTY] = {};
   // device regions inside the workspace
   DomainDev* d_doms = nullptr;
   BoxDev* d_boxes = nullptr;

@@ -510,6 +510,8 @@ __global__ __launch_bounds__(192) void k_pass_b(T* __restrict__ W, const BoxDev*
 // as its occupancy is not LDS-bound there.
 template <typename T>
 constexpr bool kPassBRing = sizeof(T) == 8;
+template <typename T>
+constexpr bool kRingPark = true;
 
 template <typename T, int NP>
 __global__ __launch_bounds__(192) void k_pass_b_ring(T* __restrict__ W,
@@ -519,6 +521,7 @@ __global__ __launch_bounds__(192) void k_pass_b_ring(T* __restrict__ W,
   constexpr int NH = NP / 2;
   static_assert(NP % 2 == 0, "size classes are even");
   __shared__ T ring[2][3][64];
+  __shared__ T park[kRingPark<T> ? 3 : 1][kRingPark<T> ? NH : 1][64];
   const int4 wk = work[xcd_remap(blockIdx.x, gridDim.x)];
   const BoxDev& B = boxes[wk.x];
   const int q = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -537,11 +540,18 @@ __global__ __launch_bounds__(192) void k_pass_b_ring(T* __restrict__ W,
   // butterfly inputs: pair j is (base + j, n - 1 - j); every load is issued
   // (at a clamped, in-column index) before any is used.  u1 is the half the
   // first sweep uses (sums for DCT-II, differences for DST-I), u2 the other.
+  // Addressed by 32-bit byte offsets from the component's (uniform) base:
+  // one VGPR per load in flight (a box component is at most 96^3 values).
   T u1[NH], u2[NH];
+  {
+    const char* cb = reinterpret_cast<const char*>(W + B.w_off + (long long)q * B.vol);
+    const unsigned c0 = (unsigned)(active ? c : 0);
 #pragma unroll
-  for (int j = 0; j < NH; ++j) {
-    u1[j] = col[(long long)min(g.base + j, nz - 1) * plane];
-    u2[j] = col[(long long)max(g.n - 1 - j, 0) * plane];
+    for (int j = 0; j < NH; ++j) {
+      const unsigned la = (unsigned)min(g.base + j, nz - 1), lb = (unsigned)max(g.n - 1 - j, 0);
+      u1[j] = *reinterpret_cast<const T*>(cb + (la * (unsigned)plane + c0) * (unsigned)sizeof(T));
+      u2[j] = *reinterpret_cast<const T*>(cb + (lb * (unsigned)plane + c0) * (unsigned)sizeof(T));
+    }
   }
 #pragma unroll
   for (int j = 0; j < NH; ++j) {
@@ -576,6 +586,13 @@ __global__ __launch_bounds__(192) void k_pass_b_ring(T* __restrict__ W,
     return fmaT<T>(alpha * sown, dot, own) * inv;
   };
 
+  // the half not used by a sweep waits in LDS: u2 during the first sweep,
+  // acc1 during the second, so that two half-length arrays are live in
+  // registers at a time (more workgroups per CU)
+  if constexpr (kRingPark<T>) {
+#pragma unroll
+    for (int j = 0; j < NH; ++j) park[q][j][lane] = u2[j];
+  }
   T acc1[NH], acc2[NH];
 #pragma unroll
   for (int j = 0; j < NH; ++j) acc1[j] = T(0);
@@ -596,6 +613,13 @@ __global__ __launch_bounds__(192) void k_pass_b_ring(T* __restrict__ W,
       for (int j = 0; j < NH; ++j) acc1[j] = fmaT<T>(row[j], e, acc1[j]);
     }
   }
+  if constexpr (kRingPark<T>) {
+#pragma unroll
+    for (int j = 0; j < NH; ++j) {
+      u2[j] = park[q][j][lane];
+      park[q][j][lane] = acc1[j];
+    }
+  }
 #pragma unroll
   for (int j = 0; j < NH; ++j) acc2[j] = T(0);
 #pragma unroll 1
@@ -613,6 +637,10 @@ __global__ __launch_bounds__(192) void k_pass_b_ring(T* __restrict__ W,
     }
   }
 
+  if constexpr (kRingPark<T>) {
+#pragma unroll
+    for (int j = 0; j < NH; ++j) acc1[j] = park[q][j][lane];
+  }
   if (active) {
 #pragma unroll
     for (int j = 0; j < NH; ++j) {

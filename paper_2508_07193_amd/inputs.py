@@ -40,8 +40,9 @@ def normal_rhs(rng, nx, ny, nz):
 
 
 def eps_table(rng, nx, ny, nz, block, lo=1.0, hi=10.0):
-    """Relative permittivity per cube of `block` cells, U[lo, hi], shape (nz/b, ny/b, nx/b)."""
-    return rng.uniform(lo, hi, size=(nz // block, ny // block, nx // block))
+    """Relative permittivity per cube of `block` cells, U[lo, hi], shape
+    (ceil(nz/b), ceil(ny/b), ceil(nx/b)): cubes cut by the far walls count whole."""
+    return rng.uniform(lo, hi, size=(-(-nz // block), -(-ny // block), -(-nx // block)))
 
 
 # Single-domain problems: n = cells per side, sub = owned subdomain side (0 = one box),

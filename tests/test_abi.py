@@ -152,3 +152,19 @@ def test_bf16_refuses_planes_beyond_its_32bit_slab_offsets(L):
     assert st == 0
     st, _ = _size(L, [flat(8192, 8192)], prec=2)         # 2^26: within range
     assert st == 0
+
+
+def test_eps_table_shape_is_checked_before_the_library_reads_it():
+    # the library reads ceil(n / b) cubes per axis from the host table: the
+    # binding refuses any other shape instead of letting it read past the array
+    import numpy as np
+    from paper_2508_07193_amd import api, inputs
+    rng = np.random.default_rng(0)
+    eps = inputs.eps_table(rng, 70, 37, 21, 4)
+    assert eps.shape == (6, 10, 18)
+    d, keep = api.domain_desc(70, 37, 21, 2.0, eps=eps, eps_block=4)
+    assert d.eps_block_size == 4 and keep.shape == (6, 10, 18)
+    with pytest.raises(ValueError, match="expected"):
+        api.domain_desc(70, 37, 21, 2.0, eps=eps[:5, :9, :17], eps_block=4)
+    with pytest.raises(ValueError, match="expected"):
+        api.domain_desc(70, 37, 21, 2.0, eps=eps, eps_block=0)

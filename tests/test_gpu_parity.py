@@ -67,7 +67,7 @@ def test_stencil_integer_inputs_bitwise():
 def test_stencil_random_eps(shape, blk, c):
     nx, ny, nz = shape
     rng = np.random.default_rng(1)
-    eps = inputs.eps_table(rng, -(-nx // blk) * blk, -(-ny // blk) * blk, -(-nz // blk) * blk, blk)
+    eps = inputs.eps_table(rng, nx, ny, nz, blk)       # ceil(n / blk) cubes per axis
     v = inputs.normal_rhs(rng, nx, ny, nz)
     ref = yee.apply_A_padded(v, c, yee.expand_eps(eps, blk, nx, ny, nz))
     h = api.Handle([dict(nx=nx, ny=ny, nz=nz, c=c, eps=eps, eps_block=blk)], device=DEV)
@@ -510,23 +510,29 @@ def test_autotune_keeps_results_bitwise():
         h.autotune(r[:h.length].contiguous())
 
 
-def test_stencil_tile_heights_agree_bitwise():
-    """The 64 x 4, 64 x 8 and 64 x 16 stencil tiles compute the same y bit for bit
-    (each is made current in turn through the plan cache)."""
+@pytest.mark.parametrize("blk", [0, 4])
+def test_stencil_tile_heights_agree_bitwise(blk):
+    """The 64 x 4, 8 and 16 stencil tiles compute the same y bit for bit,
+    with and without a permittivity table (each tile height is made current
+    in turn through the plan cache)."""
     import os
     import tempfile
     nx, ny, nz = 70, 37, 21                          # ragged against every tile height
-    P = inputs.make_problem(dict(n=(nx, ny, nz), sub=0, c=2.0, eps_block=0, seed=9))
+    P = inputs.make_problem(dict(n=(nx, ny, nz), sub=0, c=2.0, eps_block=blk, seed=9))
     x = dev(P["rhs"])
-    ref = yee.apply_A_padded(P["rhs"], 2.0)
+    dom = dict(nx=nx, ny=ny, nz=nz, c=2.0, sub=(0, 0, 0))
+    eps_cell = None
+    if blk:
+        dom.update(eps=P["eps"], eps_block=blk)
+        eps_cell = yee.expand_eps(P["eps"], blk, nx, ny, nz)
+    ref = yee.apply_A_padded(P["rhs"], 2.0, eps_cell)
     outs = []
     with tempfile.TemporaryDirectory() as d:
         path = os.path.join(d, "plans.txt")
         old = os.environ.get("FMP_TUNE_CACHE")
         os.environ["FMP_TUNE_CACHE"] = path
         try:
-            h = api.Handle([dict(nx=nx, ny=ny, nz=nz, c=2.0, sub=(0, 0, 0))], device=DEV,
-                           batch_boxes=-1)
+            h = api.Handle([dom], device=DEV, batch_boxes=-1)
             tune = h.autotune(x, h.new_vector())
             key, b, ns, so, ty = open(path).read().split()
             for t in (4, 8, 16):                     # rewrite the record, re-tune from it
