@@ -32,16 +32,16 @@ HBM_PEAK_GBS = 8000.0
 # since, traffic is null.
 TRAFFIC = {
     "k_mupdate": (1.0000, {"fmp_krylov.hip": "007a4daff79be785b7e7b45be9ae1a9a36d275d3d7dce1a34dbc36c12cb8fce5",
-                          "fmp_common.h": "5fa9b1240eca9bf5a42db978f0e817d8130fd80be6ff88cb526515b09bef99ee"}),
+                          "fmp_common.h": "29e6d322f7b76d24dd01922e0bcf5b2fd956d45b445f79172e6746defd9f6869"}),
     "k_mdot": (1.0001, {"fmp_krylov.hip": "007a4daff79be785b7e7b45be9ae1a9a36d275d3d7dce1a34dbc36c12cb8fce5",
-                        "fmp_common.h": "5fa9b1240eca9bf5a42db978f0e817d8130fd80be6ff88cb526515b09bef99ee"}),
+                        "fmp_common.h": "29e6d322f7b76d24dd01922e0bcf5b2fd956d45b445f79172e6746defd9f6869"}),
     # per stencil tile height (halo rows re-read through L2 differ by tile)
-    "k_curlcurl": ({4: 1.0412, 8: 1.0357, 16: 1.0245}, {"fmp_stencil.hip": "696e04ec48a51593d192077df34e99a631009e7660df29edde94fb7fbba8ea32",
-                            "fmp_common.h": "5fa9b1240eca9bf5a42db978f0e817d8130fd80be6ff88cb526515b09bef99ee"}),
+    "k_curlcurl": ({4: 1.0416, 8: 1.0359, 16: 1.0245}, {"fmp_stencil.hip": "696e04ec48a51593d192077df34e99a631009e7660df29edde94fb7fbba8ea32",
+                            "fmp_common.h": "29e6d322f7b76d24dd01922e0bcf5b2fd956d45b445f79172e6746defd9f6869"}),
     # the three passes of one apply over the algorithmic 16 B per unknown
-    "precond_apply": (3.5879, {"fmp_transform.hip": "088abf9b8896e3e557464f37e6c273226e17e0e0e5c5cb55a9815bd5ca2b3932",
-                               "fmp_api.hip": "0dddaf4aeaf91c2a3568c0d78d8d9f4f23d45122452cb630cbaa56bf1143d8a5",
-                               "fmp_common.h": "5fa9b1240eca9bf5a42db978f0e817d8130fd80be6ff88cb526515b09bef99ee"}),
+    "precond_apply": (3.5860, {"fmp_transform.hip": "088abf9b8896e3e557464f37e6c273226e17e0e0e5c5cb55a9815bd5ca2b3932",
+                               "fmp_api.hip": "4ddc5bea422c2fc542cf5415eaf7a5d9cbc56562fa782bfd30c72eabf7b12410",
+                               "fmp_common.h": "29e6d322f7b76d24dd01922e0bcf5b2fd956d45b445f79172e6746defd9f6869"}),
 }
 
 

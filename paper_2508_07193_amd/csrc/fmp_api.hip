@@ -127,7 +127,7 @@ long long plan_batches(fmp_ctx* h, int batch) {
             const int n = a == 0 ? B.nx : (a == 1 ? B.ny : B.nz);
             const long long ncol = B.vol / n;
             for (int q = 0; q < 3; ++q)
-              for (int it = 0; it * TI < n; ++it)
+              for (int it = 0; it * TI < large_rows(n); ++it)
                 for (long long ct = 0; ct * TC < ncol; ++ct)
                   h->work_l.push_back(make_int4(h->order[i], q, it, (int)ct));
           }
@@ -535,8 +535,10 @@ fmp_status fmp_setup_subdomains(const fmp_domain_desc* domains, int32_t n_domain
   for (int n = 2; n <= kMaxSide; ++n)
     if (sides_used[n]) side_slot[n] = nsides++;
   // per side: dct, dct^T, dst (kTS x kTS), sig (kTS), then butterfly half
-  // tables for DCT-II and DST-I (4 of kHS x kHS each: TS, TD, TS^T, TD^T)
-  const long long per_side = 3LL * kTS * kTS + kTS + 8LL * kHS * kHS;
+  // tables for DCT-II and DST-I (4 each: TS, TD, TS^T, TD^T; hs x hs with
+  // hs = kHS up to kMaxSideVec, kHL above)
+  const long long per_side = 3LL * kTS * kTS + kTS + 8LL * kHL * kHL;
+  const auto half_stride = [](int n) { return n <= kMaxSideVec ? kHS : kHL; };
   std::vector<double> tab64((size_t)(per_side * nsides), 0.0);
   {
     std::vector<double> c, s, g;
@@ -549,20 +551,21 @@ fmp_status fmp_setup_subdomains(const fmp_domain_desc* domains, int32_t n_domain
         for (int j = 0; j < kTS; ++j) base[kTS * kTS + i * kTS + j] = c[j * kTS + i];
       std::copy(s.begin(), s.end(), base + 2 * kTS * kTS);
       std::copy(g.begin(), g.end(), base + 3 * kTS * kTS);
-      for (int tau = 0; tau < 2 && n <= kMaxSideVec; ++tau) {   // vector-ALU sides only
+      const int hs = half_stride(n);
+      for (int tau = 0; tau < 2; ++tau) {
         const std::vector<double>& T = tau == 0 ? c : s;   // full n x n matrix, stride kTS
-        double* hb = base + 3 * kTS * kTS + kTS + tau * 4 * kHS * kHS;
+        double* hb = base + 3 * kTS * kTS + kTS + tau * 4 * hs * hs;
         const int P = (n - tau) / 2, mid = (n - tau) & 1, cm = (n - 1 + tau) / 2;
         for (int k = 0; k < P + mid; ++k) {
-          for (int j = 0; j < P; ++j) hb[k * kHS + j] = T[(tau + 2 * k) * kTS + tau + j];
-          if (mid) hb[k * kHS + P] = T[(tau + 2 * k) * kTS + cm];
+          for (int j = 0; j < P; ++j) hb[k * hs + j] = T[(tau + 2 * k) * kTS + tau + j];
+          if (mid) hb[k * hs + P] = T[(tau + 2 * k) * kTS + cm];
         }
         for (int k = 0; k < P; ++k)
-          for (int j = 0; j < P; ++j) hb[kHS * kHS + k * kHS + j] = T[(tau + 2 * k + 1) * kTS + tau + j];
-        for (int i = 0; i < kHS; ++i)
-          for (int j = 0; j < kHS; ++j) {
-            hb[2 * kHS * kHS + i * kHS + j] = hb[j * kHS + i];
-            hb[3 * kHS * kHS + i * kHS + j] = hb[kHS * kHS + j * kHS + i];
+          for (int j = 0; j < P; ++j) hb[hs * hs + k * hs + j] = T[(tau + 2 * k + 1) * kTS + tau + j];
+        for (int i = 0; i < hs; ++i)
+          for (int j = 0; j < hs; ++j) {
+            hb[2 * hs * hs + i * hs + j] = hb[j * hs + i];
+            hb[3 * hs * hs + i * hs + j] = hb[hs * hs + j * hs + i];
           }
       }
     }
@@ -576,8 +579,9 @@ fmp_status fmp_setup_subdomains(const fmp_domain_desc* domains, int32_t n_domain
       B.dctT[a] = base + kTS * kTS;
       B.dst[a] = base + 2 * kTS * kTS;
       B.sig[a] = base + 3 * kTS * kTS;
+      const int hs = half_stride(sides[a]);
       B.half[a][0] = base + 3 * kTS * kTS + kTS;
-      B.half[a][1] = base + 3 * kTS * kTS + kTS + 4 * kHS * kHS;
+      B.half[a][1] = base + 3 * kTS * kTS + kTS + 4 * hs * hs;
       const int mbase = side_slot[sides[a]] * 3 * kTB * kTB;
       B.mdct[a] = mbase;
       B.mdctT[a] = mbase + kTB * kTB;

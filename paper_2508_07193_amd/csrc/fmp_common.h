@@ -19,6 +19,7 @@ constexpr int kMaxSide = 96;
 constexpr int kMaxSideVec = 48;
 constexpr int kTS = 96;
 constexpr int kHS = 24;   // stride of the half (butterfly) tables, sides <= kMaxSideVec
+constexpr int kHL = 48;   // stride of the half tables of the larger sides (<= kTS)
 
 // Transform size classes: a box of largest side n runs the kernels compiled
 // for the smallest class >= n (zero-padded rows/columns cost flops only).
@@ -146,6 +147,7 @@ int pass_a_zslab(int cls);   // planes per pass-A/C work item for a class
 // staging holds two copies of each box.
 int large_tile_rows();
 int large_tile_cols();
+int large_rows(int n);      // rows (virtual, see fmp_large.hip) the contractions tile along an axis of n
 hipError_t launch_large(int prec, const double* r, void* W, double* z, const BoxDev* boxes,
                         const DomainDev* doms, const int4* work_a, int na, const int4* work_l,
                         const int* l0, const int* nl, int zs, const void* tab,
