@@ -39,7 +39,7 @@ TRAFFIC = {
     "k_curlcurl": ({4: 1.0416, 8: 1.0359, 16: 1.0245}, {"fmp_stencil.hip": "696e04ec48a51593d192077df34e99a631009e7660df29edde94fb7fbba8ea32",
                             "fmp_common.h": "29e6d322f7b76d24dd01922e0bcf5b2fd956d45b445f79172e6746defd9f6869"}),
     # the three passes of one apply over the algorithmic 16 B per unknown
-    "precond_apply": (3.5860, {"fmp_transform.hip": "088abf9b8896e3e557464f37e6c273226e17e0e0e5c5cb55a9815bd5ca2b3932",
+    "precond_apply": (3.5849, {"fmp_transform.hip": "89f6dbcd3f7ced6233c356d43fce0b30f7fc0af49ef22fa7884666d2b35dd901",
                                "fmp_api.hip": "4ddc5bea422c2fc542cf5415eaf7a5d9cbc56562fa782bfd30c72eabf7b12410",
                                "fmp_common.h": "29e6d322f7b76d24dd01922e0bcf5b2fd956d45b445f79172e6746defd9f6869"}),
 }

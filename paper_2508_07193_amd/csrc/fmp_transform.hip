@@ -197,15 +197,16 @@ __device__ __forceinline__ void inv_bfly(const T* __restrict__ tab, const Half g
   if (g.base) st(0, T(0));                        // DST-I: the wall slot
 }
 
-// Split forms for workgroups in which two threads share each pencil.  The
-// pencil is read in full by both (bfly_sums_or_diffs, inv_load), every thread
-// of the workgroup passes a barrier, then each thread computes half of the
-// outputs: the forward splits by parity (part 0 the sums' rows, i.e. the
-// outputs base + 2k, part 1 the differences' rows), the inverse by output
-// pairs (part 0 the pairs j < (P + 1) / 2, part 1 the rest and the middle
-// index).  Every output is the same row product as in fwd_bfly / inv_bfly,
-// summed in the same order, so the results are bitwise those of the
-// unsplit forms.
+// Split forms for workgroups in which S = 2 or 4 threads share each pencil.
+// The pencil is read in full by each of them (bfly_sums_or_diffs, inv_load),
+// every thread of the workgroup passes a barrier, then each thread computes
+// its share of the outputs: the forward splits by parity (even parts the
+// sums' rows, i.e. the outputs base + 2k, odd parts the differences' rows)
+// and, with four threads, each parity's rows in two halves; the inverse
+// splits the output pairs j < P into S ranges (the last part also forms the
+// middle index).  Every output is the same row product as in fwd_bfly /
+// inv_bfly, summed in the same order, so the results are bitwise those of
+// the unsplit forms.
 template <typename T, int NH, class Load>
 __device__ __forceinline__ void bfly_sums_or_diffs(const Half g, int part, Load ld, T (&u)[NH]) {
 #pragma unroll
@@ -217,19 +218,20 @@ __device__ __forceinline__ void bfly_sums_or_diffs(const Half g, int part, Load 
     } else if (j == g.P && g.mid) {
       xa = ld(g.c);
     }
-    u[j] = part == 0 ? xa + xb : xa - xb;
+    u[j] = (part & 1) == 0 ? xa + xb : xa - xb;
   }
 }
 
-template <typename T, int NH, class Store>
+template <typename T, int NH, int S, class Store>
 __device__ __forceinline__ void fwd_part(const T* __restrict__ tab, const Half g, int part,
                                          const T (&u)[NH], Store st) {
-  if (part == 0) {
-    rows_times<T, NH>(tab, g.P + g.mid, u, [&](int k, T val) { st(g.base + 2 * k, val); });
-    if (g.base) st(0, T(0));                      // DST-I: slot 0 holds no mode
-  } else {
-    rows_times<T, NH>(tab + kHS * kHS, g.P, u, [&](int k, T val) { st(g.base + 2 * k + 1, val); });
-  }
+  const int odd = part & 1, piece = part >> 1;
+  const int cnt = odd ? g.P : g.P + g.mid;
+  const int step = (cnt + S / 2 - 1) / (S / 2);
+  const int r0 = min(cnt, piece * step), r1 = min(cnt, r0 + step);
+  const T* M = tab + (odd ? kHS * kHS : 0) + r0 * kHS;
+  rows_times<T, NH>(M, r1 - r0, u, [&](int k, T val) { st(g.base + 2 * (r0 + k) + odd, val); });
+  if (part == 0 && g.base) st(0, T(0));           // DST-I: slot 0 holds no mode
 }
 
 template <typename T, int NH, class Load>
@@ -242,13 +244,13 @@ __device__ __forceinline__ void inv_load(const Half g, Load ld, T (&ys)[NH], T (
   }
 }
 
-template <typename T, int NH, class Store>
+template <typename T, int NH, int S, class Store>
 __device__ __forceinline__ void inv_part(const T* __restrict__ tab, const Half g, int part,
                                          const T (&ys)[NH], const T (&yd)[NH], Store st) {
   const T* __restrict__ TSt = tab + 2 * kHS * kHS;
   const T* __restrict__ TDt = tab + 3 * kHS * kHS;
-  const int jm = (g.P + 1) >> 1;
-  const int j0 = part == 0 ? 0 : jm, j1 = part == 0 ? jm : g.P;
+  const int jm = (g.P + S - 1) / S;
+  const int j0 = min(g.P, part * jm), j1 = min(g.P, j0 + jm);
 #pragma unroll 1
   for (int j = j0; j < j1; ++j) {
     T e, o;
@@ -256,7 +258,7 @@ __device__ __forceinline__ void inv_part(const T* __restrict__ tab, const Half g
     st(g.base + j, e + o);
     st(g.n - 1 - j, e - o);
   }
-  if (part == 1 && g.mid) st(g.c, row_dot<T, NH>(TSt + g.P * kHS, ys));
+  if (part == S - 1 && g.mid) st(g.c, row_dot<T, NH>(TSt + g.P * kHS, ys));
   if (part == 0 && g.base) st(0, T(0));           // DST-I: the wall slot
 }
 
@@ -285,7 +287,9 @@ __device__ __forceinline__ bool box_wall(int q, int x, int y, int z) {
 // pencil's outputs), which doubles the waves per CU at the same LDS: at the
 // 512 boxes of 34^3 of a 256^3 grid, FP64 pass A 347 -> 273 us and pass C
 // 319 -> 274 us, FP32 pass A 216 -> 186 us.  FP32 pass C keeps one thread
-// per pencil (its split form needs 104 VGPRs: 232 us against 177 us).
+// per pencil (its split form needs 104 VGPRs: 232 us against 177 us).  Four
+// threads per pencil (512-thread workgroups) fit three FP64 workgroups per
+// CU instead of five: pass A 334 us (FP32 224 us).
 constexpr int kAC = 128;
 template <int NP>
 constexpr int zslab() {
@@ -304,7 +308,8 @@ __global__ __launch_bounds__(NTH) void k_pass_a(const double* __restrict__ r, T*
                                                 const DomainDev* __restrict__ doms,
                                                 const int4* __restrict__ work,
                                                 const T* __restrict__ tab) {
-  static_assert(NTH == kAC || NTH == 2 * kAC, "one or two threads per pencil");
+  static_assert(NTH == kAC || NTH == 2 * kAC || NTH == 4 * kAC, "1, 2 or 4 threads per pencil");
+  constexpr int S = NTH / kAC;
   constexpr int ZS = zslab<NP>();
   constexpr int MAXE = (ZS * NP * NP + NTH - 1) / NTH;
   constexpr int NH = NP / 2;
@@ -365,21 +370,21 @@ __global__ __launch_bounds__(NTH) void k_pass_a(const double* __restrict__ r, T*
                       [&](int p, T v) { dst[p * nx] = v; });
     }
   } else {
-    // two threads per pencil: waves 0-1 form the even outputs, waves 2-3 the odd ones
+    // S threads per pencil: waves 2p, 2p + 1 form part p of the outputs
     const int part = __builtin_amdgcn_readfirstlane(t / kAC);
     const int u = t - part * kAC;
     T hv[NH];
     T* row = buf + u * nx;
     if (u < nzs * ny) bfly_sums_or_diffs<T, NH>(gx, part, [&](int l) { return row[l]; }, hv);
     __syncthreads();                              // the row is overwritten in place
-    if (u < nzs * ny) fwd_part<T, NH>(tabx, gx, part, hv, [&](int p, T v) { row[p] = v; });
+    if (u < nzs * ny) fwd_part<T, NH, S>(tabx, gx, part, hv, [&](int p, T v) { row[p] = v; });
     __syncthreads();
     if (u < nzs * nx) {
       const int zl = u / nx, x = u - zl * nx;
       const T* colp = buf + zl * plane + x;
       T* dst = dst0 + zl * plane + x;
       bfly_sums_or_diffs<T, NH>(gy, part, [&](int m) { return colp[m * nx]; }, hv);
-      fwd_part<T, NH>(taby, gy, part, hv, [&](int p, T v) { dst[p * nx] = v; });
+      fwd_part<T, NH, S>(taby, gy, part, hv, [&](int p, T v) { dst[p * nx] = v; });
     }
   }
 }
@@ -665,7 +670,8 @@ __global__ __launch_bounds__(NTH) void k_pass_c(const T* __restrict__ W, double*
                                                 const int4* __restrict__ work,
                                                 const T* __restrict__ tab,
                                                 const double* __restrict__ coarse, int nsub) {
-  static_assert(NTH == kAC || NTH == 2 * kAC, "one or two threads per pencil");
+  static_assert(NTH == kAC || NTH == 2 * kAC || NTH == 4 * kAC, "1, 2 or 4 threads per pencil");
+  constexpr int S = NTH / kAC;
   constexpr int ZS = zslab<NP>();
   constexpr int MAXE = (ZS * NP * NP + NTH - 1) / NTH;
   constexpr int NH = NP / 2;
@@ -706,9 +712,9 @@ __global__ __launch_bounds__(NTH) void k_pass_c(const T* __restrict__ W, double*
       inv_bfly<T, NH>(tabx, gx, [&](int p) { return row[p]; }, [&](int l, T v) { row[l] = v; });
     }
   } else {
-    // two threads per pencil: waves 0-1 form the outputs of the first half of
-    // the butterfly pairs, waves 2-3 the rest; each pencil is read in full by
-    // both before either overwrites it
+    // S threads per pencil: waves 2p, 2p + 1 form the outputs of the p-th
+    // range of butterfly pairs; each pencil is read in full by all of them
+    // before any overwrites it
     const int part = __builtin_amdgcn_readfirstlane(t / kAC);
     const int u = t - part * kAC;
     T ys[NH], yd[NH];
@@ -718,13 +724,13 @@ __global__ __launch_bounds__(NTH) void k_pass_c(const T* __restrict__ W, double*
       if (u < nzs * nx) inv_load<T, NH>(gy, [&](int m) { return colp[m * nx]; }, ys, yd);
       __syncthreads();
       if (u < nzs * nx)
-        inv_part<T, NH>(taby, gy, part, ys, yd, [&](int m, T v) { colp[m * nx] = v; });
+        inv_part<T, NH, S>(taby, gy, part, ys, yd, [&](int m, T v) { colp[m * nx] = v; });
     }
     __syncthreads();
     T* row = buf + u * nx;
     if (u < nzs * ny) inv_load<T, NH>(gx, [&](int p) { return row[p]; }, ys, yd);
     __syncthreads();
-    if (u < nzs * ny) inv_part<T, NH>(tabx, gx, part, ys, yd, [&](int l, T v) { row[l] = v; });
+    if (u < nzs * ny) inv_part<T, NH, S>(tabx, gx, part, ys, yd, [&](int l, T v) { row[l] = v; });
   }
   __syncthreads();
 

@@ -75,6 +75,8 @@ LARGE_CASES = [
     (124, 62, 4, 1),          # 8 boxes of 63 cells with overlap (class 64)
     (100, 50, 0, 2),          # 8 boxes of 52 cells, overlap 2 (class 64)
     (150, 75, 0, 1),          # 8 boxes of 76 cells (class 96), ragged GEMM tiles
+    (49, 0, 7, 1),            # one box of 49 cells: the smallest large side, odd
+    (95, 0, 5, 1),            # one box of 95 cells: odd, the butterfly's middle index
 ]
 
 
