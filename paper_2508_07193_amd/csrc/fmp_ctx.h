@@ -47,6 +47,7 @@ struct IBPlan {
   long long stage_elems = 0;   // W_E + W_C region (also the unit-solve staging at setup)
   int unit_batch = 0;
   int m_max = 0, mp_max = 0;
+  int gemv_kr = 1024;          // rows of C^{-1} per k-range of the C^{-1} h step
   long long vol_max = 0;
   BoxDev* d_boxes = nullptr;
   double* d_tab = nullptr;

@@ -302,12 +302,13 @@ __global__ __launch_bounds__(256) void k_ib_fill(double* __restrict__ p, long lo
 // so h_i = sum_k C^{-1}[k][i] g_k streams rows of C^{-1}.  An item (matrix,
 // first output i0, first entry in the grouped box list, count) and a k-range
 // index (blockIdx.y) own outputs i0 .. i0 + 255 for the item's boxes and
-// rows k of one range of kGR: every row is read as one 2 KB contiguous
-// segment (a thread per output column), 16 rows in flight per thread, and
-// the g values of 64 rows at a time sit in LDS.  Partial sums per range go
-// to `part` and k_ib_creduce adds the ranges in a fixed order.
+// rows k of one range of kr (a multiple of 64, chosen at setup so that the
+// launch has enough workgroups to fill the GPU): every row is read as one
+// 2 KB contiguous segment (a thread per output column), 16 rows in flight
+// per thread, and the g values of 64 rows at a time sit in LDS.  Partial
+// sums per range go to `part` and k_ib_creduce adds the ranges in a fixed
+// order.
 constexpr int kGC = 256;    // output columns per item
-constexpr int kGR = 1024;   // rows of C^{-1} per k-range
 constexpr int kGG = 64;     // g rows staged per step
 __global__ __launch_bounds__(256) void k_ib_cgemv(const double* __restrict__ Cinv,
                                                   const IBCorrDev* __restrict__ corr,
@@ -315,13 +316,13 @@ __global__ __launch_bounds__(256) void k_ib_cgemv(const double* __restrict__ Cin
                                                   const int* __restrict__ gbox,
                                                   const BoxDev* __restrict__ boxes,
                                                   const double* __restrict__ g, int ngbox,
-                                                  int m_max, double* __restrict__ part) {
+                                                  int m_max, int kr, double* __restrict__ part) {
   __shared__ double gs[kGG][16];
   const int4 it = items[blockIdx.x];
   const IBCorrDev C = corr[it.x];
-  const int kb = blockIdx.y * kGR;
+  const int kb = blockIdx.y * kr;
   if (kb >= C.m) return;                          // this matrix has fewer ranges
-  const int ke = min(kb + kGR, C.m);
+  const int ke = min(kb + kr, C.m);
   const int t = threadIdx.x;
   const int i = it.y + t;
   const bool valid = i < C.m;
@@ -355,12 +356,12 @@ __global__ __launch_bounds__(256) void k_ib_creduce(const double* __restrict__ p
                                                     const IBCorrDev* __restrict__ corr,
                                                     const int* __restrict__ gbox,
                                                     const BoxDev* __restrict__ boxes,
-                                                    int ngbox, int m_max,
+                                                    int ngbox, int m_max, int kr,
                                                     double* __restrict__ hv) {
   const int e = blockIdx.y;
   const BoxDev& B = boxes[gbox[e]];
   const int m = B.m;
-  const int nr = (m + kGR - 1) / kGR;
+  const int nr = (m + kr - 1) / kr;
   for (int i = blockIdx.x * 256 + threadIdx.x; i < m; i += gridDim.x * 256) {
     double s = 0.0;
     for (int r = 0; r < nr; ++r) s += part[((long long)r * ngbox + e) * m_max + i];
@@ -799,6 +800,12 @@ fmp_status ib_prepare(fmp_ctx* h) {
       for (int i0 = 0; i0 < P.corr[k].m; i0 += kGC)
         P.gemv.push_back(make_int4((int)k, i0, first + b0, std::min(16, cnt - b0)));
   }
+  // k-range: the longest (fewest partial sums) that still gives the launch
+  // about 2048 workgroups (8 per CU)
+  P.gemv_kr = 1024;
+  while (P.gemv_kr > 256 &&
+         (long long)P.gemv.size() * ((P.m_max + P.gemv_kr - 1) / P.gemv_kr) < 2048)
+    P.gemv_kr /= 2;
   // setup batches of unit solves reuse the W_E + W_C region
   P.unit_batch = std::max(1, std::min(P.m_max, 128));
   P.stage_elems = std::max(2 * P.w_elems, (long long)P.unit_batch * ((3 * vmax + 7) / 8 * 8));
@@ -807,7 +814,7 @@ fmp_status ib_prepare(fmp_ctx* h) {
 
 // partial sums of the C^{-1} h step: k-ranges x grouped boxes x m_max
 static size_t gemv_part_elems(const IBPlan& P) {
-  const size_t nr = (size_t)(P.m_max + kGR - 1) / kGR;
+  const size_t nr = (size_t)(P.m_max + P.gemv_kr - 1) / P.gemv_kr;
   return nr * P.gbox.size() * (size_t)P.m_max;
 }
 
@@ -975,11 +982,11 @@ fmp_status ib_apply(fmp_ctx* h, const double* r, double* z, hipStream_t s) {
     // g = Q^T E, h = C^{-1} g, W_C = Q h
     const int mblk = std::max(1, std::min(64, (P.m_max + 255) / 256));
     hipLaunchKernelGGL(k_ib_qgather, dim3(mblk, nbox), dim3(256), 0, s, P.d_WE, P.d_boxes, P.d_qidx, P.d_g);
-    const int nr = (P.m_max + kGR - 1) / kGR, ngb = (int)P.gbox.size();
+    const int kr = P.gemv_kr, nr = (P.m_max + kr - 1) / kr, ngb = (int)P.gbox.size();
     hipLaunchKernelGGL(k_ib_cgemv, dim3((int)P.gemv.size(), nr), dim3(256), 0, s, P.d_cinv,
-                       P.d_corr, P.d_gemv, P.d_gbox, P.d_boxes, P.d_g, ngb, P.m_max, P.d_part);
+                       P.d_corr, P.d_gemv, P.d_gbox, P.d_boxes, P.d_g, ngb, P.m_max, kr, P.d_part);
     hipLaunchKernelGGL(k_ib_creduce, dim3(std::min(64, (P.m_max + 255) / 256), ngb), dim3(256), 0,
-                       s, P.d_part, P.d_corr, P.d_gbox, P.d_boxes, ngb, P.m_max, P.d_hv);
+                       s, P.d_part, P.d_corr, P.d_gbox, P.d_boxes, ngb, P.m_max, kr, P.d_hv);
     hipLaunchKernelGGL(k_ib_fill, dim3(blocks_for(P.w_elems)), dim3(256), 0, s, P.d_WC, P.w_elems, 0.0);
     hipLaunchKernelGGL(k_ib_qscatter, dim3(mblk, nbox), dim3(256), 0, s, P.d_hv, P.d_boxes, P.d_qidx, P.d_WC);
     IBCHK(hipGetLastError());
