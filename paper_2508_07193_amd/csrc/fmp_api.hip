@@ -806,7 +806,7 @@ fmp_status fmp_apply_precond(fmp_handle h, const double* r, double* z, void* str
   if (!h || !r || !z) return FMP_ERR_INVALID_ARG;
   if (overlaps(r, z, h->len * 8)) return FMP_ERR_ALIAS;
   if (!h->precond_ok) {
-    h->err = "a box side exceeds the largest compiled transform size (48 cells with FP64 or FP32 transforms, 96 with BF16)";
+    h->err = "a box side exceeds the largest compiled transform size (96 cells for PEC boxes, 48 for index blocks)";
     return FMP_ERR_UNSUPPORTED;
   }
   hipStream_t s = (hipStream_t)stream;
