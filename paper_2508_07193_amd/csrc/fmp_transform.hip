@@ -20,6 +20,8 @@
 // class) and read the transform matrix through the scalar unit: every lane of
 // a wave multiplies by the same matrix entry, so each FMA takes one SGPR
 // operand and the matrix costs no vector registers or LDS bandwidth.
+#include <type_traits>
+
 #include "fmp_common.h"
 
 namespace fmp {
@@ -301,6 +303,26 @@ constexpr int zslab() {
 // issued before any is consumed (addresses clamped in bounds, results
 // selected afterwards): the kernels are latency-bound otherwise.
 
+// Calls f(n, tau) with the transform length n and the butterfly base tau as
+// compile-time constants when n is NP or NP - 1 (the box sides of a class
+// at the usual splits), so that the butterfly's index arithmetic folds into
+// immediate offsets; other lengths take plain integers.  Used by pass A
+// (FP64 at 256^3: 271 -> 252..262 us); in pass C the constant forms raise
+// the register count from 85 to 151 (333 us), so it keeps the run-time form.
+template <int NP, class F>
+__device__ __forceinline__ void with_len(int n, int tau, F&& f) {
+  using std::integral_constant;
+  if (tau == 0) {
+    if (n == NP) f(integral_constant<int, NP>{}, integral_constant<int, 0>{});
+    else if (n == NP - 1) f(integral_constant<int, NP - 1>{}, integral_constant<int, 0>{});
+    else f(n, 0);
+  } else {
+    if (n == NP) f(integral_constant<int, NP>{}, integral_constant<int, 1>{});
+    else if (n == NP - 1) f(integral_constant<int, NP - 1>{}, integral_constant<int, 1>{});
+    else f(n, 1);
+  }
+}
+
 // ---------------------------------------------------------------- pass A
 template <typename T, int NP, int NTH>
 __global__ __launch_bounds__(NTH) void k_pass_a(const double* __restrict__ r, T* __restrict__ W,
@@ -375,16 +397,22 @@ __global__ __launch_bounds__(NTH) void k_pass_a(const double* __restrict__ r, T*
     const int u = t - part * kAC;
     T hv[NH];
     T* row = buf + u * nx;
-    if (u < nzs * ny) bfly_sums_or_diffs<T, NH>(gx, part, [&](int l) { return row[l]; }, hv);
-    __syncthreads();                              // the row is overwritten in place
-    if (u < nzs * ny) fwd_part<T, NH, S>(tabx, gx, part, hv, [&](int p, T v) { row[p] = v; });
+    with_len<NP>(nx, q == 0 ? 0 : 1, [&](auto n, auto tau) __attribute__((always_inline)) {
+      const Half g = half_geom(n, tau);
+      if (u < nzs * ny) bfly_sums_or_diffs<T, NH>(g, part, [&](int l) { return row[l]; }, hv);
+      __syncthreads();                            // the row is overwritten in place
+      if (u < nzs * ny) fwd_part<T, NH, S>(tabx, g, part, hv, [&](int p, T v) { row[p] = v; });
+    });
     __syncthreads();
     if (u < nzs * nx) {
       const int zl = u / nx, x = u - zl * nx;
       const T* colp = buf + zl * plane + x;
       T* dst = dst0 + zl * plane + x;
-      bfly_sums_or_diffs<T, NH>(gy, part, [&](int m) { return colp[m * nx]; }, hv);
-      fwd_part<T, NH, S>(taby, gy, part, hv, [&](int p, T v) { dst[p * nx] = v; });
+      with_len<NP>(ny, q == 1 ? 0 : 1, [&](auto n, auto tau) __attribute__((always_inline)) {
+        const Half g = half_geom(n, tau);
+        bfly_sums_or_diffs<T, NH>(g, part, [&](int m) { return colp[m * nx]; }, hv);
+        fwd_part<T, NH, S>(taby, g, part, hv, [&](int p, T v) { dst[p * nx] = v; });
+      });
     }
   }
 }
