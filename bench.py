@@ -36,11 +36,11 @@ TRAFFIC = {
     "k_mdot": (1.0001, {"fmp_krylov.hip": "007a4daff79be785b7e7b45be9ae1a9a36d275d3d7dce1a34dbc36c12cb8fce5",
                         "fmp_common.h": "29e6d322f7b76d24dd01922e0bcf5b2fd956d45b445f79172e6746defd9f6869"}),
     # per stencil tile height (halo rows re-read through L2 differ by tile)
-    "k_curlcurl": ({4: 1.0416, 8: 1.0359, 16: 1.0245}, {"fmp_stencil.hip": "696e04ec48a51593d192077df34e99a631009e7660df29edde94fb7fbba8ea32",
+    "k_curlcurl": ({4: 1.0421, 8: 1.033, 16: 1.0328}, {"fmp_stencil.hip": "696e04ec48a51593d192077df34e99a631009e7660df29edde94fb7fbba8ea32",
                             "fmp_common.h": "29e6d322f7b76d24dd01922e0bcf5b2fd956d45b445f79172e6746defd9f6869"}),
     # the three passes of one apply over the algorithmic 16 B per unknown
-    "precond_apply": (3.5849, {"fmp_transform.hip": "89f6dbcd3f7ced6233c356d43fce0b30f7fc0af49ef22fa7884666d2b35dd901",
-                               "fmp_api.hip": "4ddc5bea422c2fc542cf5415eaf7a5d9cbc56562fa782bfd30c72eabf7b12410",
+    "precond_apply": (3.5876, {"fmp_transform.hip": "92b08a71867dd340626a44a7c120e50eab4fe3e9cf9e8635ddcf9ff43aee4264",
+                               "fmp_api.hip": "ab429b9713259a736ab153a5d4bfbee3b645f3914d45851014d0860fc257729e",
                                "fmp_common.h": "29e6d322f7b76d24dd01922e0bcf5b2fd956d45b445f79172e6746defd9f6869"}),
 }
 
