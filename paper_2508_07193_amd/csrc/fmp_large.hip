@@ -142,22 +142,25 @@ __global__ __launch_bounds__(kLT) void k_lg_contract(T* __restrict__ W,
   const long long bs = buf_stride(B);
   const T* src = W + B.w_off + (long long)from * bs + (long long)q * B.vol;
   T* dst = W + B.w_off + (long long)(1 - from) * bs + (long long)q * B.vol;
-  const T* TS = tab + B.half[axis][tau];          // kHL x kHL each: TS, TD, TS^T, TD^T
-  const T* TD = TS + kHL * kHL;
-  const T* TSt = TS + 2 * kHL * kHL;
-  const T* TDt = TS + 3 * kHL * kHL;
+  // half tables TS, TD, TS^T, TD^T, hs x hs each: the side's own stride
+  // (a large box can have sides of 48 cells or fewer on its other axes)
+  const int hs = n <= kMaxSideVec ? kHS : kHL;
+  const T* TS = tab + B.half[axis][tau];
+  const T* TD = TS + hs * hs;
+  const T* TSt = TS + 2 * hs * hs;
+  const T* TDt = TS + 3 * hs * hs;
   const int t = threadIdx.x;
   const int ti = t >> 4, tj = t & 15;
   // table row of virtual row v, or null for a padding row
   auto arow = [&](int v) -> const T* {
     if constexpr (!inverse) {
-      if (v < NSp) return v < g.NS ? TS + v * kHL : nullptr;
+      if (v < NSp) return v < g.NS ? TS + v * hs : nullptr;
       v -= NSp;
-      return v < g.P ? TD + v * kHL : nullptr;
+      return v < g.P ? TD + v * hs : nullptr;
     }
     const int j = 2 * (v >> 2) + (v & 1);
     if (j >= g.NS) return nullptr;
-    return (v & 2) ? TDt + j * kHL : TSt + j * kHL;
+    return (v & 2) ? TDt + j * hs : TSt + j * hs;
   };
   // forward: a thread's four rows read the differences when they are odd
   // outputs; inverse: rows 0, 1 read the even coefficients, rows 2, 3 the odd

@@ -122,6 +122,32 @@ def test_fp32_large_boxes_within_bound(n, sub, blk, overlap):
     assert np.all(out[~inputs.unknown_slots(n, n, n)] == 0.0)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_large_box_with_short_sides(precision):
+    """A box of 70 x 20 x 12 cells (one box over a non-cubic domain): the
+    large-box path runs every axis, the short ones with the small sides'
+    half tables (stride 24), the long one with stride 48."""
+    nx, ny, nz, c = 70, 20, 12, 2.0
+    rng = np.random.default_rng(70)
+    eps = inputs.eps_table(rng, nx, ny, nz, 4)
+    eps_cell = yee.expand_eps(eps, 4, nx, ny, nz)
+    r = inputs.normal_rhs(rng, nx, ny, nz)
+    h = api.Handle([dict(nx=nx, ny=ny, nz=nz, c=c, eps=eps, eps_block=4, sub=(0, 0, 0))],
+                   precision=precision, device=DEV)
+    z = h.new_vector()
+    h.apply_precond(dev(r), z)
+    ref = ras.ras_apply(r, c, (nx, ny, nz), 1, eps_cell)
+    out = host(z, ref.shape)
+    h.close()
+    if precision == "fp64":
+        err = np.abs(out - ref).max() / np.abs(ref).max()
+        assert err <= 1e-12, err
+    else:
+        err = rel2(out, ref)
+        assert err < 24 * 2.0**-24, err
+    assert np.all(out[~inputs.unknown_slots(nx, ny, nz)] == 0.0)
+
+
 def test_boxes_above_96_are_refused():
     for prec in ("fp64", "fp32", "bf16"):
         h = api.Handle([dict(nx=128, ny=128, nz=128, c=1.0, sub=(0, 0, 0))], precision=prec,
