@@ -335,7 +335,6 @@ __global__ __launch_bounds__(NTH) void k_pass_a(const double* __restrict__ r, T*
   constexpr int ZS = zslab<NP>();
   constexpr int MAXE = (ZS * NP * NP + NTH - 1) / NTH;
   constexpr int NH = NP / 2;
-  static_assert(MAXE <= 64, "wall flags are kept in one 64-bit mask");
   __shared__ T buf[ZS * NP * NP];
   const int4 wk = work[xcd_remap(blockIdx.x, gridDim.x)];
   const BoxDev& B = boxes[wk.x];
@@ -351,6 +350,12 @@ __global__ __launch_bounds__(NTH) void k_pass_a(const double* __restrict__ r, T*
   // S^gamma: gather the slab.  A thread's elements t + NTH i are stepped from
   // its first one by the fixed increment of NTH elements (two carries), with
   // no per-element division; loads of out-of-slab steps read element 0.
+  // The box's wall slots (slot 0 of a node axis) are copied as they come:
+  // the DST-I along that axis reads slots 1 .. n-1 only and writes zero to
+  // its slot 0, and a wall row or plane feeds, through the transforms of the
+  // other axes, only outputs at that same wall slot, which the DST-I along
+  // the wall's own axis (here or in pass B) never reads.  So no value read
+  // from a wall slot reaches a consumed coefficient.
   const double* s0 = src + ((long long)(B.bz0 + z0) * D.ny + B.by0) * D.nx + B.bx0;
   int zl = t / plane, y = (t - zl * plane) / nx, x = t - zl * plane - y * nx;
   const int dz = NTH / plane, rk = NTH - dz * plane, dy = rk / nx, dx = rk - dy * nx;
@@ -358,19 +363,17 @@ __global__ __launch_bounds__(NTH) void k_pass_a(const double* __restrict__ r, T*
   const int doff = (dz * D.ny + dy) * D.nx + dx;
   const int cx_off = D.nx - nx, cy_off = (D.ny - ny) * D.nx;
   double vals[MAXE];
-  unsigned long long wall = 0;
 #pragma unroll
   for (int i = 0; i < MAXE; ++i) {
     vals[i] = s0[t + NTH * i < tot ? off : 0];
-    if (box_wall(q, x, y, z0 + zl)) wall |= 1ull << i;
-    x += dx; y += dy; zl += dz; off += doff;
+    x += dx; y += dy; off += doff;
     if (x >= nx) { x -= nx; ++y; off += cx_off; }
-    if (y >= ny) { y -= ny; ++zl; off += cy_off; }
+    if (y >= ny) { y -= ny; off += cy_off; }
   }
 #pragma unroll
   for (int i = 0; i < MAXE; ++i) {
     const int e = t + NTH * i;
-    if (e < tot) buf[e] = ((wall >> i) & 1ull) ? T(0) : (T)vals[i];
+    if (e < tot) buf[e] = (T)vals[i];
   }
   __syncthreads();
 
