@@ -57,7 +57,7 @@ typedef enum {
   FMP_ERR_WORKSPACE = -3,     /* workspace missing, too small or misaligned     */
   FMP_ERR_HIP = -4,           /* a HIP runtime call failed                       */
   FMP_ERR_BREAKDOWN = -5,     /* Krylov breakdown or non-finite value           */
-  FMP_ERR_UNSUPPORTED = -6    /* valid request this build does not implement    */
+  FMP_ERR_UNSUPPORTED = -6    /* valid request the library does not implement   */
 } fmp_status;
 
 typedef enum { FMP_FP64 = 0, FMP_FP32 = 1, FMP_BF16 = 2 } fmp_precision;
