@@ -119,6 +119,47 @@ def test_precond_fp64_matches_oracle(n, sub, c, blk, overlap):
     assert np.all(out[~inputs.unknown_slots(n, n, n)] == 0.0)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("n,sub", [(48, 16), (64, 0)])   # 27 boxes of 17/18; one box of 64
+def test_precond_ignores_nonfinite_wall_slots(prec, n, sub):
+    """Wall slots of r are outside the unknown set: NaN and +-Inf there must
+    leave z bitwise as with zeros there.  The vector-ALU passes copy the wall
+    slots into the transform staging unmasked (every DST-I skips its slot 0),
+    so this checks that no such value reaches a consumed coefficient; the
+    BF16 and large-box paths zero them on the gather."""
+    P = problem(n, sub, 2.0, 8, seed=n + 7)
+    h = handle_for(P, precision=prec)
+    r = P["rhs"].copy()
+    wall = ~inputs.unknown_slots(n, n, n)
+    bad = r.copy()
+    vals = np.array([np.nan, np.inf, -np.inf])
+    bad[wall] = vals[np.arange(int(wall.sum())) % 3]
+    z0, z1 = h.new_vector(), h.new_vector()
+    h.apply_precond(dev(r), z0)
+    h.apply_precond(dev(bad), z1)
+    a, b = host(z0, r.shape), host(z1, r.shape)
+    assert np.all(np.isfinite(b))
+    assert np.array_equal(a, b)
+
+
+def test_stencil_ignores_nonfinite_wall_slots():
+    """The same for y = A x (default 64 x 8 tiles; the staging that masks
+    the wall slots is common to every tile height)."""
+    nx, ny, nz = 70, 21, 19
+    rng = np.random.default_rng(8)
+    x = inputs.normal_rhs(rng, nx, ny, nz)
+    wall = ~inputs.unknown_slots(nx, ny, nz)
+    bad = x.copy()
+    bad[wall] = np.array([np.nan, np.inf, -np.inf])[np.arange(int(wall.sum())) % 3]
+    eps = inputs.eps_table(rng, nx, ny, nz, 4)
+    h = api.Handle([dict(nx=nx, ny=ny, nz=nz, c=2.0, eps=eps, eps_block=4)], device=DEV)
+    y0, y1 = h.new_vector(), h.new_vector()
+    h.curlcurl_apply(dev(x), y0)
+    h.curlcurl_apply(dev(bad), y1)
+    a, b = host(y0, x.shape), host(y1, x.shape)
+    assert np.all(np.isfinite(b)) and np.array_equal(a, b)
+
+
 def test_precond_anisotropic_domain():
     nx, ny, nz, sub, c = 48, 32, 24, (16, 16, 8), 1.5
     rng = np.random.default_rng(5)
