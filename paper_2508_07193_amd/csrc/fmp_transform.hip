@@ -277,6 +277,18 @@ __device__ __forceinline__ double recip<double>(double d) {
   return r;
 }
 
+// the same with one Newton step: the estimate's relative error e becomes
+// about e^2, below the FP64 rounding for the estimate's accuracy
+template <typename T>
+__device__ __forceinline__ T recip1(T d) {
+  return T(1) / d;
+}
+template <>
+__device__ __forceinline__ double recip1<double>(double d) {
+  const double r = __builtin_amdgcn_rcp(d);
+  return __builtin_fma(__builtin_fma(-d, r, 1.0), r, r);
+}
+
 // slot 0 of a component's node axes is the box wall
 __device__ __forceinline__ bool box_wall(int q, int x, int y, int z) {
   return q == 0 ? (y == 0 || z == 0) : (q == 1 ? (x == 0 || z == 0) : (x == 0 || y == 0));
@@ -566,7 +578,6 @@ __global__ __launch_bounds__(192) void k_pass_b_ring(T* __restrict__ W,
   const int plane = ny * nx;
   const int c = wk.y + lane;
   const bool active = c < plane;
-  T* col = W + B.w_off + (long long)q * B.vol + (active ? c : 0);
   const int tz = q == 2 ? 0 : 1;                  // DCT-II along z for E_z, DST-I otherwise
   const T* __restrict__ TS = tab + B.half[2][tz];
   const T* __restrict__ TD = TS + kHS * kHS;
@@ -616,7 +627,7 @@ __global__ __launch_bounds__(192) void k_pass_b_ring(T* __restrict__ W,
     const T a = ring[sl][0][lane], b = ring[sl][1][lane], d = ring[sl][2][lane];
     const T s3 = sz[rr];
     const T dot = fmaT<T>(sx, a, fmaT<T>(sy, b, s3 * d));
-    const T inv = recip<T>(fmaT<T>(alpha, fmaT<T>(s3, s3, sxy2), T(1)));
+    const T inv = recip1<T>(fmaT<T>(alpha, fmaT<T>(s3, s3, sxy2), T(1)));
     const T own = q == 0 ? a : (q == 1 ? b : d);
     const T sown = q == 0 ? sx : (q == 1 ? sy : s3);
     return fmaT<T>(alpha * sown, dot, own) * inv;
@@ -678,18 +689,24 @@ __global__ __launch_bounds__(192) void k_pass_b_ring(T* __restrict__ W,
     for (int j = 0; j < NH; ++j) acc1[j] = park[q][j][lane];
   }
   if (active) {
+    // stores by 32-bit byte offsets from the component's base, as the loads
+    char* cbw = reinterpret_cast<char*>(W + B.w_off + (long long)q * B.vol);
+    const unsigned c0 = (unsigned)c;
+    auto at = [&](int l) -> T& {
+      return *reinterpret_cast<T*>(cbw + ((unsigned)l * (unsigned)plane + c0) * (unsigned)sizeof(T));
+    };
 #pragma unroll
     for (int j = 0; j < NH; ++j) {
       const T ev = tz == 0 ? acc1[j] : acc2[j];   // sums' (even) part
       const T od = tz == 0 ? acc2[j] : acc1[j];   // differences' (odd) part
       if (j < g.P) {
-        col[(long long)(g.base + j) * plane] = ev + od;
-        col[(long long)(g.n - 1 - j) * plane] = ev - od;
+        at(g.base + j) = ev + od;
+        at(g.n - 1 - j) = ev - od;
       } else if (j == g.P && g.mid) {
-        col[(long long)g.c * plane] = ev;
+        at(g.c) = ev;
       }
     }
-    if (g.base) col[0] = T(0);                    // DST-I: the wall slot
+    if (g.base) at(0) = T(0);                     // DST-I: the wall slot
   }
 }
 
