@@ -31,15 +31,15 @@ HBM_PEAK_GBS = 8000.0
 # for the kernel sources it was measured on: if any listed source changed
 # since, traffic is null.
 TRAFFIC = {
-    "k_mupdate": (1.0000, {"fmp_krylov.hip": "007a4daff79be785b7e7b45be9ae1a9a36d275d3d7dce1a34dbc36c12cb8fce5",
+    "k_mupdate": (1.0000, {"fmp_krylov.hip": "2d8ce5abd17a3d4d663922d953a4ffdb81ffb46d83ff33b0d1ea22998bc560f2",
                           "fmp_common.h": "29e6d322f7b76d24dd01922e0bcf5b2fd956d45b445f79172e6746defd9f6869"}),
-    "k_mdot": (1.0001, {"fmp_krylov.hip": "007a4daff79be785b7e7b45be9ae1a9a36d275d3d7dce1a34dbc36c12cb8fce5",
+    "k_mdot": (1.0001, {"fmp_krylov.hip": "2d8ce5abd17a3d4d663922d953a4ffdb81ffb46d83ff33b0d1ea22998bc560f2",
                         "fmp_common.h": "29e6d322f7b76d24dd01922e0bcf5b2fd956d45b445f79172e6746defd9f6869"}),
     # per stencil tile height (halo rows re-read through L2 differ by tile)
-    "k_curlcurl": ({4: 1.0417, 8: 1.0325, 16: 1.0246}, {"fmp_stencil.hip": "696e04ec48a51593d192077df34e99a631009e7660df29edde94fb7fbba8ea32",
+    "k_curlcurl": ({4: 1.0413, 8: 1.0322, 16: 1.0328}, {"fmp_stencil.hip": "696e04ec48a51593d192077df34e99a631009e7660df29edde94fb7fbba8ea32",
                             "fmp_common.h": "29e6d322f7b76d24dd01922e0bcf5b2fd956d45b445f79172e6746defd9f6869"}),
     # the three passes of one apply over the algorithmic 16 B per unknown
-    "precond_apply": (3.4233, {"fmp_transform.hip": "1fd580dd3750853635c6fee20f8de2ff42a81f7f4203ffe14ffdc80f2f2ae432",
+    "precond_apply": (3.5960, {"fmp_transform.hip": "1fd580dd3750853635c6fee20f8de2ff42a81f7f4203ffe14ffdc80f2f2ae432",
                                "fmp_api.hip": "ab429b9713259a736ab153a5d4bfbee3b645f3914d45851014d0860fc257729e",
                                "fmp_common.h": "29e6d322f7b76d24dd01922e0bcf5b2fd956d45b445f79172e6746defd9f6869"}),
 }

@@ -240,22 +240,22 @@ __global__ __launch_bounds__(kThreads) void k_scale_seg(const double* __restrict
 
 // Per-segment fixed-order reduction: thread t sums partial blocks b0 + t,
 // b0 + t + 256, ... of its segment; waves and then the block combine in order.
+// One workgroup per (segment, column): the columns, each summed in the same
+// fixed order, go in parallel rather than one after another.
 __global__ __launch_bounds__(kThreads) void k_reduce_seg(const double* __restrict__ partials,
-                                                         int n, const SegDev* __restrict__ segs,
+                                                         const SegDev* __restrict__ segs,
                                                          double* __restrict__ out, int ostride) {
   __shared__ double red[4];
   const SegDev sg = segs[blockIdx.x];
+  const int i = blockIdx.y;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  for (int i = 0; i < n; ++i) {
-    const double* p = partials + (long long)i * kRedBlocks + sg.b0;
-    double v = 0.0;
-    for (int k = t; k < sg.nb; k += kThreads) v += p[k];
-    v = wave_sum(v);
-    if (lane == 0) red[wave] = v;
-    __syncthreads();
-    if (t == 0) out[(long long)blockIdx.x * ostride + i] = ((red[0] + red[1]) + red[2]) + red[3];
-    __syncthreads();
-  }
+  const double* p = partials + (long long)i * kRedBlocks + sg.b0;
+  double v = 0.0;
+  for (int k = t; k < sg.nb; k += kThreads) v += p[k];
+  v = wave_sum(v);
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  if (t == 0) out[(long long)blockIdx.x * ostride + i] = ((red[0] + red[1]) + red[2]) + red[3];
 }
 
 // post-op codes of the final reduction
@@ -480,7 +480,7 @@ hipError_t launch_reduce(const double* partials, int n, double* out, int post, d
 hipError_t launch_reduce_seg(const double* partials, int n, const SegDev* segs, int nseg,
                              double* out, int ostride, hipStream_t s) {
   if (n < 1 || n > kMaxDots || nseg < 1 || nseg > kRedBlocks) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_reduce_seg, dim3(nseg), dim3(kThreads), 0, s, partials, n, segs, out,
+  hipLaunchKernelGGL(k_reduce_seg, dim3(nseg, n), dim3(kThreads), 0, s, partials, segs, out,
                      ostride);
   return hipGetLastError();
 }
