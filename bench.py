@@ -39,7 +39,7 @@ TRAFFIC = {
     "k_curlcurl": ({4: 1.0413, 8: 1.0322, 16: 1.0328}, {"fmp_stencil.hip": "696e04ec48a51593d192077df34e99a631009e7660df29edde94fb7fbba8ea32",
                             "fmp_common.h": "29e6d322f7b76d24dd01922e0bcf5b2fd956d45b445f79172e6746defd9f6869"}),
     # the three passes of one apply over the algorithmic 16 B per unknown
-    "precond_apply": (3.5960, {"fmp_transform.hip": "f81f90a7ec66c74fe6ca76b1971bb387b7d1b2530e27020085129e163c4df1a5",
+    "precond_apply": (3.5960, {"fmp_transform.hip": "451b2ffc4bca4d36a132b61d611652d0d7c2de1e1144a15cd2ff955cf703e5ac",
                                "fmp_api.hip": "ab429b9713259a736ab153a5d4bfbee3b645f3914d45851014d0860fc257729e",
                                "fmp_common.h": "29e6d322f7b76d24dd01922e0bcf5b2fd956d45b445f79172e6746defd9f6869"}),
 }

@@ -264,28 +264,16 @@ __device__ __forceinline__ void inv_part(const T* __restrict__ tab, const Half g
   if (part == 0 && g.base) st(0, T(0));           // DST-I: the wall slot
 }
 
+// 1/d for d >= 1 (the 3x3 solve's 1 + alpha |s|^2): a division in FP32; in
+// FP64 the hardware estimate and one Newton step, which squares the
+// estimate's relative error: the FP64 apply's error against the exact solve
+// stays where it is with two steps (about 2e-15 relative on a 16^3 domain)
 template <typename T>
 __device__ __forceinline__ T recip(T d) {
   return T(1) / d;
 }
-// 1/d for d >= 1 from the hardware estimate and two Newton steps
 template <>
 __device__ __forceinline__ double recip<double>(double d) {
-  double r = __builtin_amdgcn_rcp(d);
-  r = __builtin_fma(__builtin_fma(-d, r, 1.0), r, r);
-  r = __builtin_fma(__builtin_fma(-d, r, 1.0), r, r);
-  return r;
-}
-
-// the same with one Newton step, which squares the hardware estimate's
-// relative error: the FP64 apply's error against the exact solve stays
-// where it is with two (about 2e-15 relative on a 16^3 domain)
-template <typename T>
-__device__ __forceinline__ T recip1(T d) {
-  return T(1) / d;
-}
-template <>
-__device__ __forceinline__ double recip1<double>(double d) {
   const double r = __builtin_amdgcn_rcp(d);
   return __builtin_fma(__builtin_fma(-d, r, 1.0), r, r);
 }
@@ -628,7 +616,7 @@ __global__ __launch_bounds__(192) void k_pass_b_ring(T* __restrict__ W,
     const T a = ring[sl][0][lane], b = ring[sl][1][lane], d = ring[sl][2][lane];
     const T s3 = sz[rr];
     const T dot = fmaT<T>(sx, a, fmaT<T>(sy, b, s3 * d));
-    const T inv = recip1<T>(fmaT<T>(alpha, fmaT<T>(s3, s3, sxy2), T(1)));
+    const T inv = recip<T>(fmaT<T>(alpha, fmaT<T>(s3, s3, sxy2), T(1)));
     const T own = q == 0 ? a : (q == 1 ? b : d);
     const T sown = q == 0 ? sx : (q == 1 ? sy : s3);
     return fmaT<T>(alpha * sown, dot, own) * inv;
