@@ -40,7 +40,7 @@ TRAFFIC = {
                             "fmp_common.h": "29e6d322f7b76d24dd01922e0bcf5b2fd956d45b445f79172e6746defd9f6869"}),
     # the three passes of one apply over the algorithmic 16 B per unknown
     "precond_apply": (3.5960, {"fmp_transform.hip": "451b2ffc4bca4d36a132b61d611652d0d7c2de1e1144a15cd2ff955cf703e5ac",
-                               "fmp_api.hip": "ab429b9713259a736ab153a5d4bfbee3b645f3914d45851014d0860fc257729e",
+                               "fmp_api.hip": "7115c5d95370c97565f6ce717e935680f02323ad55970b187b67041eca2ca2a6",
                                "fmp_common.h": "29e6d322f7b76d24dd01922e0bcf5b2fd956d45b445f79172e6746defd9f6869"}),
 }
 

@@ -32,9 +32,6 @@ constexpr int kTB = 96;         // row stride of the bf16 tables (largest class)
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 constexpr int kScal = 256;      // doubles in the scalar area
-constexpr int kScalH = 16;      // h column of FGMRES
-constexpr int kScalW = 64;      // ||w||^2
-constexpr int kScalY = 128;     // FGMRES update coefficients
 constexpr int kScalJ = 200;     // learned-correction residual test: ||v - w||^2, ||v - w + A d||^2
 // per-group scalar block (kSD doubles per group)
 constexpr int kSD = 192;
